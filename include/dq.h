@@ -1,0 +1,169 @@
+/*
+ * dq.h - C ABI of libdq, the MI355X (gfx950) dual-quantisation library.
+ *
+ * Dual-quantisation is the prediction/quantisation step of SZ as re-designed
+ * by cuSZ and studied in "SIMD Lossy Compression for Scientific Data" (Dube
+ * et al., arXiv 2201.04614), Section III-A:
+ *
+ *   compress    q = round(x / (2 eb))                   pre-quantisation
+ *               delta = q - Lorenzo prediction of q      inside fixed-size
+ *                       from its lower neighbours         blocks, the block
+ *                       in the same block                 padding forming the
+ *                                                         halo (Section IV)
+ *               code = delta + R   if -R < delta < R     post-quantisation
+ *               else code = 0 and (index, delta) is an outlier
+ *   decompress  the inverse: outlier scatter, a blockwise n-D prefix sum of
+ *               delta plus the block's effective padding, and
+ *               x_hat = (float)((double)q * 2 eb).
+ *
+ * Every result is exact integer or IEEE arithmetic and is defined uniquely:
+ *  - q is the nearest integer to the exact rational x / (2 eb), exact halves
+ *    to even, so |x - 2 eb q| <= eb for every element; |q| <= 2^31 - 1;
+ *  - arithmetic on q and delta wraps modulo 2^32 (the inverse is exact);
+ *  - padding values are integer means of q, rounded to nearest with halves
+ *    toward +infinity (Section IV-A: a statistic of the data; IV-B: one value
+ *    per field, per block, or per block and axis). The EDGE value of axis a
+ *    is the mean of the block's own cells whose local coordinate along a is
+ *    0; a halo cell in front of the block along several axes takes the
+ *    rounded mean of those axes' values;
+ *  - blocks are cubic (edge B along every axis of the field), aligned at the
+ *    origin, truncated at the high end of each axis;
+ *  - outliers are listed block by block (blocks in row-major order of the
+ *    block grid), cells in local row-major order; indices are C-order linear
+ *    indices into the field (uint32).
+ *
+ * Memory: every buffer is owned by the caller. Pointers named x, codes,
+ * out_idx, out_val, pads, x_hat, res and ws are DEVICE pointers (hipMalloc
+ * or torch CUDA tensors); params and res_host are host pointers. The library
+ * allocates nothing and keeps no mutable global state; calls on different
+ * streams with different buffers may run concurrently.
+ *
+ * Streams: dq_compress and dq_decompress validate on the host, then enqueue
+ * their kernels on hip_stream (a hipStream_t; NULL = the null stream) and
+ * return without waiting. Device-side outcomes (status, outlier count, the
+ * absolute error bound used) are written to the device-resident dq_result;
+ * dq_result_sync copies it to the host and waits for the stream.
+ *
+ * Errors are returned, never thrown. A host-side error means nothing was
+ * enqueued.
+ */
+#ifndef DQ_H
+#define DQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DQ_OK = 0,
+    DQ_EINVAL = -1,     /* invalid parameter, null pointer, workspace too small,
+                           or (device) a relative bound over a zero value range */
+    DQ_ERANGE = -2,     /* (device) non-finite input, or |q| > 2^31 - 1 */
+    DQ_ECAPACITY = -3,  /* (device) more outliers than out_cap; n_out is exact */
+    DQ_ENOTSUP = -4,    /* valid but not supported by the GPU kernels (block
+                           not a power of two, or beyond the supported edge) */
+    DQ_EDEVICE = -5,    /* a HIP runtime call failed */
+    DQ_ECORRUPT = -6    /* (device, decompress) codes and outliers disagree */
+} dq_status;
+
+typedef enum { DQ_EB_ABS = 0, DQ_EB_REL = 1 } dq_eb_mode;
+
+typedef enum {
+    DQ_PAD_ZERO = 0,        /* no side data */
+    DQ_PAD_BLOCK_MEAN = 1,  /* one int32 per block */
+    DQ_PAD_EDGE_MEAN = 2,   /* ndim int32 per block, axis-major inside a block */
+    DQ_PAD_GLOBAL_MEAN = 3  /* one int32 */
+} dq_pad_mode;
+
+/* Field and codec parameters.
+ *  ndim      1, 2 or 3
+ *  shape     extents, shape[0] slowest (C order); entries >= ndim ignored;
+ *            product < 2^32
+ *  eb        absolute bound (DQ_EB_ABS) or factor of the value range
+ *            max(x) - min(x) (DQ_EB_REL), finite and > 0
+ *  block     block edge B >= 1 (GPU: a power of two, B <= 4096 in 1-D,
+ *            B <= 256 in 2-D, B <= 64 in 3-D)
+ *  pad_mode  dq_pad_mode
+ *  radius    R in [1, 32768]: codes are uint16, 0 marks an outlier */
+typedef struct {
+    int32_t ndim;
+    int32_t eb_mode;
+    int64_t shape[3];
+    double eb;
+    int32_t block;
+    int32_t pad_mode;
+    int32_t radius;
+    int32_t reserved; /* set to 0 */
+} dq_params;
+
+/* Device-resident outcome of one call. */
+typedef struct {
+    int32_t status;   /* dq_status */
+    uint32_t reserved;
+    uint64_t n_out;   /* exact number of outliers (compress) */
+    double eb_abs;    /* absolute error bound used (compress) */
+} dq_result;
+
+/* Optional timing hooks: hipEvent_t handles recorded on hip_stream right
+ * before and right after the call's main kernel (encode or decode).
+ * Either may be NULL. */
+typedef struct {
+    void *ev_before;
+    void *ev_after;
+} dq_hooks;
+
+/* Host-only parameter check (no GPU needed): DQ_OK, DQ_EINVAL or DQ_ENOTSUP. */
+dq_status dq_validate(const dq_params *p);
+
+/* Number of blocks of the field. */
+dq_status dq_num_blocks(const dq_params *p, uint64_t *n_blocks);
+
+/* Number of int32 padding values: 0 (ZERO), 1 (GLOBAL_MEAN), n_blocks
+ * (BLOCK_MEAN), n_blocks * ndim (EDGE_MEAN). */
+dq_status dq_pad_count(const dq_params *p, uint64_t *n_pads);
+
+/* Device workspace (bytes, 256-byte aligned start) needed by dq_compress
+ * with room for out_cap outliers, and by dq_decompress. */
+dq_status dq_compress_workspace(const dq_params *p, uint64_t out_cap, uint64_t *bytes);
+dq_status dq_decompress_workspace(const dq_params *p, uint64_t *bytes);
+
+/* Compress x (N fp32, C order) into codes (N uint16, C order), the outlier
+ * list out_idx/out_val (room for out_cap entries, block-major order) and pads
+ * (dq_pad_count int32). out_idx/out_val may be NULL when out_cap == 0; pads
+ * may be NULL when dq_pad_count is 0. res receives status, n_out, eb_abs.
+ * If n_out > out_cap the status is DQ_ECAPACITY, the codes are complete, the
+ * outlier list is not, and n_out is exact: retry with out_cap >= n_out.
+ * x, codes and ws must not overlap any other buffer. */
+dq_status dq_compress(const dq_params *p, const float *x, uint16_t *codes,
+                      uint32_t *out_idx, int32_t *out_val, uint64_t out_cap,
+                      int32_t *pads, dq_result *res, void *ws, uint64_t ws_bytes,
+                      void *hip_stream, const dq_hooks *hooks);
+
+/* Decompress into x_hat (N fp32). eb_abs is the absolute bound reported by
+ * compress; p->eb and p->eb_mode are ignored. n_out entries of out_idx/out_val
+ * are read. res->status becomes DQ_ECORRUPT if an outlier index is out of
+ * range or out of block-major order, a zero code has no outlier, or an
+ * outlier sits on a non-zero code; x_hat is then unspecified. */
+dq_status dq_decompress(const dq_params *p, double eb_abs, const uint16_t *codes,
+                        const uint32_t *out_idx, const int32_t *out_val, uint64_t n_out,
+                        const int32_t *pads, float *x_hat, dq_result *res,
+                        void *ws, uint64_t ws_bytes, void *hip_stream,
+                        const dq_hooks *hooks);
+
+/* Copy a device dq_result to the host after waiting for hip_stream. */
+dq_status dq_result_sync(const dq_result *res_dev, dq_result *res_host, void *hip_stream);
+
+/* hipEvent helpers for dq_hooks (timing events, no allocation on the device). */
+dq_status dq_event_create(void **ev);
+dq_status dq_event_destroy(void *ev);
+dq_status dq_event_elapsed_ms(void *ev_before, void *ev_after, float *ms);
+
+/* Static description of a status code. */
+const char *dq_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,319 @@
+// dq_api.hip - host side of libdq: parameter validation, geometry, workspace
+// layout and the launch sequence of dq_compress / dq_decompress.
+#include <math.h>
+#include <string.h>
+
+#include "../../include/dq.h"
+#include "dq_kernels.hpp"
+
+using namespace dq;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+inline uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int ilog2(uint32_t v) {
+    int l = 0;
+    while ((1u << l) < v) ++l;
+    return l;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Host check shared by every entry point. check_eb is false for decompress,
+// which takes the absolute bound separately.
+dq_status validate(const dq_params* p, bool check_eb) {
+    if (!p) return DQ_EINVAL;
+    if (p->ndim < 1 || p->ndim > 3) return DQ_EINVAL;
+    double total = 1.0;
+    for (int a = 0; a < p->ndim; ++a) {
+        if (p->shape[a] < 1) return DQ_EINVAL;
+        total *= (double)p->shape[a];
+    }
+    if (total > 4294967295.0) return DQ_EINVAL;
+    if (check_eb) {
+        if (!(p->eb > 0.0) || !isfinite(p->eb)) return DQ_EINVAL;
+        if (p->eb_mode != DQ_EB_ABS && p->eb_mode != DQ_EB_REL) return DQ_EINVAL;
+        if (p->eb_mode == DQ_EB_ABS && !isfinite(1.0 / (2.0 * p->eb))) return DQ_EINVAL;
+    }
+    if (p->block < 1) return DQ_EINVAL;
+    if (p->pad_mode < DQ_PAD_ZERO || p->pad_mode > DQ_PAD_GLOBAL_MEAN) return DQ_EINVAL;
+    if (p->radius < 1 || p->radius > 32768) return DQ_EINVAL;
+    // GPU kernel coverage
+    const int maxb = p->ndim == 1 ? 4096 : (p->ndim == 2 ? 256 : 64);
+    if (!is_pow2(p->block) || p->block > maxb) return DQ_ENOTSUP;
+    return DQ_OK;
+}
+
+struct Plan {
+    Geom g;
+    int dim, B, V;
+    uint64_t nblocks;
+};
+
+void base_geom(const dq_params* p, Geom& g) {
+    const int d = p->ndim;
+    const uint32_t B = (uint32_t)p->block;
+    g.nx = (uint32_t)p->shape[d - 1];
+    g.ny = d >= 2 ? (uint32_t)p->shape[d - 2] : 1u;
+    g.nz = d == 3 ? (uint32_t)p->shape[0] : 1u;
+    g.nbx = (g.nx + B - 1) / B;
+    g.nby = (g.ny + B - 1) / B;
+    g.nbz = (g.nz + B - 1) / B;
+    g.nblocks = g.nbx * g.nby * g.nbz;
+    g.N = (uint64_t)g.nx * g.ny * g.nz;
+}
+
+bool finish_plan(const dq_params* p, int V, Plan& pl) {
+    const int bpt = tile_blocks(p->ndim, p->block, V);
+    if (bpt <= 0) return false;
+    base_geom(p, pl.g);
+    if (pl.g.nx % (uint32_t)V != 0) return false;
+    pl.g.bpt = (uint32_t)bpt;
+    pl.g.ntx = (pl.g.nbx + (uint32_t)bpt - 1) / (uint32_t)bpt;
+    const uint64_t tiles = (uint64_t)pl.g.ntx * pl.g.nby * pl.g.nbz;
+    if (tiles > 0xffffffffull) return false;
+    pl.g.n_tiles = (uint32_t)tiles;
+    pl.dim = p->ndim;
+    pl.B = p->block;
+    pl.V = V;
+    pl.nblocks = pl.g.nblocks;
+    return true;
+}
+
+// Widest vector width V that the field and the buffers allow.
+bool make_plan(const dq_params* p, const void* fptr, const void* cptr, Plan& pl) {
+    const uintptr_t fa = reinterpret_cast<uintptr_t>(fptr);
+    const uintptr_t ca = reinterpret_cast<uintptr_t>(cptr);
+    for (int V = 4; V >= 1; V >>= 1) {
+        if ((fa % (4u * V)) != 0 || (ca % (2u * V)) != 0) continue;
+        if (finish_plan(p, V, pl)) return true;
+    }
+    return false;
+}
+
+uint64_t max_tiles(const dq_params* p) {
+    uint64_t m = 0;
+    for (int V = 1; V <= 4; V <<= 1) {
+        Plan pl;
+        if (finish_plan(p, V, pl) && pl.g.n_tiles > m) m = pl.g.n_tiles;
+    }
+    return m;
+}
+
+struct CompressLayout {
+    uint64_t sc, tiles, info, stage, total;
+};
+
+CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
+    Geom g;
+    base_geom(p, g);
+    const uint64_t cap = out_cap < g.N ? out_cap : g.N;
+    CompressLayout L;
+    L.sc = 0;
+    L.tiles = align_up(sizeof(Scalars));
+    L.info = L.tiles + align_up(4 * max_tiles(p));
+    L.stage = L.info + align_up(4ull * g.nblocks);
+    L.total = L.stage + align_up(16 * cap);
+    return L;
+}
+
+dq_status check_launch() {
+    return hipGetLastError() == hipSuccess ? DQ_OK : DQ_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+dq_status dq_validate(const dq_params* p) { return validate(p, true); }
+
+dq_status dq_num_blocks(const dq_params* p, uint64_t* n_blocks) {
+    dq_status st = validate(p, false);
+    if (st != DQ_OK && st != DQ_ENOTSUP) return st;
+    if (!n_blocks) return DQ_EINVAL;
+    uint64_t nb = 1;
+    for (int a = 0; a < p->ndim; ++a) nb *= (uint64_t)((p->shape[a] + p->block - 1) / p->block);
+    *n_blocks = nb;
+    return DQ_OK;
+}
+
+dq_status dq_pad_count(const dq_params* p, uint64_t* n_pads) {
+    uint64_t nb = 0;
+    dq_status st = dq_num_blocks(p, &nb);
+    if (st != DQ_OK) return st;
+    if (!n_pads) return DQ_EINVAL;
+    switch (p->pad_mode) {
+    case DQ_PAD_ZERO: *n_pads = 0; break;
+    case DQ_PAD_GLOBAL_MEAN: *n_pads = 1; break;
+    case DQ_PAD_BLOCK_MEAN: *n_pads = nb; break;
+    default: *n_pads = nb * (uint64_t)p->ndim; break;
+    }
+    return DQ_OK;
+}
+
+dq_status dq_compress_workspace(const dq_params* p, uint64_t out_cap, uint64_t* bytes) {
+    dq_status st = validate(p, true);
+    if (st != DQ_OK) return st;
+    if (!bytes) return DQ_EINVAL;
+    *bytes = compress_layout(p, out_cap).total;
+    return DQ_OK;
+}
+
+dq_status dq_decompress_workspace(const dq_params* p, uint64_t* bytes) {
+    dq_status st = validate(p, false);
+    if (st != DQ_OK) return st;
+    if (!bytes) return DQ_EINVAL;
+    Geom g;
+    base_geom(p, g);
+    *bytes = align_up(4ull * ((uint64_t)g.nblocks + 1));
+    return DQ_OK;
+}
+
+dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint32_t* out_idx,
+                      int32_t* out_val, uint64_t out_cap, int32_t* pads, dq_result* res, void* ws,
+                      uint64_t ws_bytes, void* hip_stream, const dq_hooks* hooks) {
+    dq_status st = validate(p, true);
+    if (st != DQ_OK) return st;
+    uint64_t npads = 0;
+    dq_pad_count(p, &npads);
+    if (!x || !codes || !res || !ws) return DQ_EINVAL;
+    if (out_cap > 0 && (!out_idx || !out_val)) return DQ_EINVAL;
+    if (npads > 0 && !pads) return DQ_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return DQ_EINVAL;
+    Plan pl;
+    if (!make_plan(p, x, codes, pl)) return DQ_ENOTSUP;
+    const CompressLayout L = compress_layout(p, out_cap);
+    if (ws_bytes < L.total) return DQ_EINVAL;
+    const uint64_t cap = out_cap < pl.g.N ? out_cap : pl.g.N;
+
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    char* w = static_cast<char*>(ws);
+    Scalars* sc = reinterpret_cast<Scalars*>(w + L.sc);
+    uint32_t* tiles = reinterpret_cast<uint32_t*>(w + L.tiles);
+    uint32_t* info = reinterpret_cast<uint32_t*>(w + L.info);
+    uint4* stage = reinterpret_cast<uint4*>(w + L.stage);
+    int32_t* status = &res->status;
+
+    launch_compress_init(sc, status, res, p->eb, p->eb, p->eb_mode, stream);
+    AuxArgs aa{x, sc, status, pl.g.N};
+    if (p->eb_mode == DQ_EB_REL) {
+        launch_minmax(aa, stream);
+        launch_resolve_rel(sc, status, res, stream);
+    }
+    if (p->pad_mode == DQ_PAD_GLOBAL_MEAN) launch_sumq(aa, stream);
+
+    EncArgs ea;
+    ea.x = x;
+    ea.codes = codes;
+    ea.pads = pads;
+    ea.block_info = info;
+    ea.tile_count = tiles;
+    ea.stage = stage;
+    ea.stage_cap = (uint32_t)cap;
+    ea.sc = sc;
+    ea.status = status;
+    ea.g = pl.g;
+    ea.R = p->radius;
+    ea.pad_mode = p->pad_mode;
+    const dim3 grid((pl.g.n_tiles + kWaves - 1) / kWaves);
+    if (hooks && hooks->ev_before) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_before), stream);
+    if (!launch_encode(pl.dim, pl.B, pl.V, ea, grid, stream)) return DQ_ENOTSUP;
+    if (hooks && hooks->ev_after) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_after), stream);
+    launch_scan_tiles(tiles, pl.g.n_tiles, sc, status, res, out_cap, stream);
+    if (cap > 0) launch_scatter(stage, (uint32_t)cap, sc, status, tiles, info, pl.g, out_idx, out_val, stream);
+    return check_launch();
+}
+
+dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes, const uint32_t* out_idx,
+                        const int32_t* out_val, uint64_t n_out, const int32_t* pads, float* x_hat,
+                        dq_result* res, void* ws, uint64_t ws_bytes, void* hip_stream,
+                        const dq_hooks* hooks) {
+    dq_status st = validate(p, false);
+    if (st != DQ_OK) return st;
+    if (!(eb_abs > 0.0) || !isfinite(eb_abs)) return DQ_EINVAL;
+    uint64_t npads = 0;
+    dq_pad_count(p, &npads);
+    if (!codes || !x_hat || !res) return DQ_EINVAL;
+    if (n_out > 0 && (!out_idx || !out_val || !ws)) return DQ_EINVAL;
+    if (npads > 0 && !pads) return DQ_EINVAL;
+    Plan pl;
+    if (!make_plan(p, x_hat, codes, pl)) return DQ_ENOTSUP;
+    if (n_out > pl.g.N) return DQ_EINVAL;
+    uint64_t need = 0;
+    dq_decompress_workspace(p, &need);
+    if (n_out > 0 && ws_bytes < need) return DQ_EINVAL;
+
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    uint32_t* block_start = static_cast<uint32_t*>(ws);
+    int32_t* status = &res->status;
+    launch_decompress_init(res, n_out, eb_abs, stream);
+    if (n_out > 0)
+        launch_index(out_idx, (uint32_t)n_out, pl.g, ilog2((uint32_t)pl.B), pl.dim, block_start, status, stream);
+
+    DecArgs da;
+    da.codes = codes;
+    da.out_idx = out_idx;
+    da.out_val = out_val;
+    da.pads = pads;
+    da.block_start = block_start;
+    da.x_hat = x_hat;
+    da.status = status;
+    da.g = pl.g;
+    da.twoeb = 2.0 * eb_abs;
+    da.n_out = (uint32_t)n_out;
+    da.R = p->radius;
+    da.pad_mode = p->pad_mode;
+    const dim3 grid((pl.g.n_tiles + kWaves - 1) / kWaves);
+    if (hooks && hooks->ev_before) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_before), stream);
+    if (!launch_decode(pl.dim, pl.B, pl.V, da, grid, stream)) return DQ_ENOTSUP;
+    if (hooks && hooks->ev_after) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_after), stream);
+    return check_launch();
+}
+
+dq_status dq_result_sync(const dq_result* res_dev, dq_result* res_host, void* hip_stream) {
+    if (!res_dev || !res_host) return DQ_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipMemcpyAsync(res_host, res_dev, sizeof(dq_result), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return DQ_EDEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return DQ_EDEVICE;
+    return DQ_OK;
+}
+
+dq_status dq_event_create(void** ev) {
+    if (!ev) return DQ_EINVAL;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return DQ_EDEVICE;
+    *ev = reinterpret_cast<void*>(e);
+    return DQ_OK;
+}
+
+dq_status dq_event_destroy(void* ev) {
+    if (!ev) return DQ_EINVAL;
+    return hipEventDestroy(reinterpret_cast<hipEvent_t>(ev)) == hipSuccess ? DQ_OK : DQ_EDEVICE;
+}
+
+dq_status dq_event_elapsed_ms(void* ev_before, void* ev_after, float* ms) {
+    if (!ev_before || !ev_after || !ms) return DQ_EINVAL;
+    if (hipEventSynchronize(reinterpret_cast<hipEvent_t>(ev_after)) != hipSuccess) return DQ_EDEVICE;
+    return hipEventElapsedTime(ms, reinterpret_cast<hipEvent_t>(ev_before),
+                               reinterpret_cast<hipEvent_t>(ev_after)) == hipSuccess
+               ? DQ_OK
+               : DQ_EDEVICE;
+}
+
+const char* dq_strerror(int status) {
+    switch (status) {
+    case DQ_OK: return "ok";
+    case DQ_EINVAL: return "invalid argument";
+    case DQ_ERANGE: return "value out of range (non-finite input or |q| > 2^31-1)";
+    case DQ_ECAPACITY: return "more outliers than the outlier capacity";
+    case DQ_ENOTSUP: return "configuration not supported by the GPU kernels";
+    case DQ_EDEVICE: return "HIP runtime error";
+    case DQ_ECORRUPT: return "codes and outliers are inconsistent";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

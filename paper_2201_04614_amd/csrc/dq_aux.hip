@@ -1,0 +1,366 @@
+// dq_aux.hip - small kernels around the encode/decode passes (gfx950).
+//
+//  compress:   init -> [REL] min/max pass + bound resolution -> [GLOBAL] sum
+//              of q -> encode -> scan of per-tile outlier counts -> scatter of
+//              the staged outliers into block-major order
+//  decompress: init -> [n_out > 0] per-block start of the outlier list (and
+//              validation of its order) -> decode
+// Status words are written with plain stores of one error value; the only
+// device errors of a compress call are EINVAL/ERANGE (before or during encode)
+// and ECAPACITY (decided by the scan when no other error occurred); decode
+// only reports ECORRUPT.
+#include "dq_device.hpp"
+#include "dq_kernels.hpp"
+
+namespace dq {
+
+struct ResultDev {
+    int32_t status;
+    uint32_t reserved;
+    unsigned long long n_out;
+    double eb_abs;
+};
+
+__device__ __forceinline__ void store_status(int32_t* status, int v) {
+    __hip_atomic_store(status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int load_status(const int32_t* status) {
+    return __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ compress init
+
+__global__ void k_compress_init(Scalars* sc, ResultDev* res, double eb, double rel, int eb_mode) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc->stage_count = 0;
+    sc->sumq = 0;
+    sc->kmin = 0xffffffffu;
+    sc->kmax = 0u;
+    sc->nonfinite = 0;
+    sc->rel = rel;
+    sc->gpad = 0;
+    res->status = ST_OK;
+    res->reserved = 0;
+    res->n_out = 0;
+    if (eb_mode == 0) {
+        sc->eb = eb;
+        sc->twoeb = 2.0 * eb;
+        sc->r = 1.0 / (2.0 * eb);
+        res->eb_abs = eb;
+    } else {
+        sc->eb = 0.0;
+        sc->twoeb = 0.0;
+        sc->r = 0.0;
+        res->eb_abs = 0.0;
+    }
+}
+
+void launch_compress_init(Scalars* sc, int32_t* status, void* res, double eb, double rel, int eb_mode,
+                          hipStream_t stream) {
+    (void)status;
+    hipLaunchKernelGGL(k_compress_init, dim3(1), dim3(64), 0, stream, sc, (ResultDev*)res, eb, rel, eb_mode);
+}
+
+// ------------------------------------------------------------------ value range (REL bound)
+
+// order-preserving map of a finite float to uint32
+__device__ __forceinline__ uint32_t fkey(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float funkey(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N, Scalars* sc, int vec4) {
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    bool nf = false;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t start = 0;
+    if (vec4) {
+        const uint64_t n4 = N / 4;
+        const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
+        for (uint64_t i = tid; i < n4; i += stride) {
+            const f32x4 v = __builtin_nontemporal_load(x4 + i);
+            const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool fin = __builtin_isfinite(e[j]);
+                nf |= !fin;
+                const uint32_t k = fkey(e[j]);
+                kmin = fin ? min(kmin, k) : kmin;
+                kmax = fin ? max(kmax, k) : kmax;
+            }
+        }
+        start = n4 * 4;
+    }
+    for (uint64_t i = start + tid; i < N; i += stride) {
+        const float e = x[i];
+        const bool fin = __builtin_isfinite(e);
+        nf |= !fin;
+        const uint32_t k = fkey(e);
+        kmin = fin ? min(kmin, k) : kmin;
+        kmax = fin ? max(kmax, k) : kmax;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+    }
+    const uint64_t anynf = ballot(nf);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&sc->kmin, kmin);
+        atomicMax(&sc->kmax, kmax);
+        if (anynf) atomicOr(&sc->nonfinite, 1u);
+    }
+}
+
+void launch_minmax(const AuxArgs& a, hipStream_t stream) {
+    const int vec4 = ((reinterpret_cast<uintptr_t>(a.x) & 15u) == 0) ? 1 : 0;
+    uint64_t work = vec4 ? a.N / 4 : a.N;
+    uint64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_minmax, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, vec4);
+}
+
+// Relative bound (Section II-B, value-range relative): eb = rel * (max - min).
+__global__ void k_resolve_rel(Scalars* sc, ResultDev* res) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (sc->nonfinite) {
+        res->status = ST_ERANGE;
+        return;
+    }
+    const double mn = (double)funkey(sc->kmin);
+    const double mx = (double)funkey(sc->kmax);
+    const double eb = sc->rel * (mx - mn);
+    const double r = 1.0 / (2.0 * eb);
+    if (!(eb > 0.0) || !__builtin_isfinite(eb) || !__builtin_isfinite(r)) {
+        res->status = ST_EINVAL;
+        return;
+    }
+    sc->eb = eb;
+    sc->twoeb = 2.0 * eb;
+    sc->r = r;
+    res->eb_abs = eb;
+}
+
+void launch_resolve_rel(Scalars* sc, int32_t* status, void* res, hipStream_t stream) {
+    (void)status;
+    hipLaunchKernelGGL(k_resolve_rel, dim3(1), dim3(64), 0, stream, sc, (ResultDev*)res);
+}
+
+// ------------------------------------------------------------------ global mean of q
+
+__global__ __launch_bounds__(256) void k_sumq(const float* __restrict__ x, uint64_t N, Scalars* sc,
+                                              int32_t* status) {
+    if (load_status(status) != ST_OK) return;
+    const double r = sc->r, twoeb = sc->twoeb, eb = sc->eb;
+    long long s = 0;
+    bool bad = false;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // uniform trip count so the wave-wide near-half check in prequant sees all lanes
+    const uint64_t iters = (N + stride - 1) / stride;
+    for (uint64_t it = 0; it < iters; ++it) {
+        const uint64_t i = tid + it * stride;
+        float v[1] = {i < N ? x[i] : 0.0f};
+        uint32_t q[1];
+        prequant<1>(v, r, twoeb, eb, q, bad);
+        s += (int32_t)q[0];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    const uint64_t anybad = ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&sc->sumq, (unsigned long long)s);
+        if (anybad) store_status(status, ST_ERANGE);
+    }
+}
+
+void launch_sumq(const AuxArgs& a, hipStream_t stream) {
+    uint64_t blocks = (a.N + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sumq, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, a.status);
+}
+
+// ------------------------------------------------------------------ scan of tile counts
+
+// Single workgroup, exclusive scan in place; writes n_out and the capacity
+// verdict.
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* cnt, uint32_t n, Scalars* sc, ResultDev* res,
+                                                     uint64_t out_cap) {
+    __shared__ uint32_t wsum[16];
+    __shared__ unsigned long long carry_s;
+    constexpr int K = 8;  // items per thread per pass
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < n; base += 1024ull * K) {
+        uint32_t v[K];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t i = base + (uint64_t)tid * K + k;
+            v[k] = i < n ? cnt[i] : 0u;
+            s += v[k];
+        }
+        const uint32_t incl = wave_scan_incl(s, lane);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int w = 0; w < wave; ++w) wbase += wsum[w];
+        const unsigned long long carry = carry_s;
+        uint32_t run = (uint32_t)carry + wbase + incl - s;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t i = base + (uint64_t)tid * K + k;
+            if (i < n) cnt[i] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (tid == 1023) {
+            uint32_t tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            carry_s = carry + tot;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const unsigned long long total = carry_s;
+        const int st = load_status(&res->status);
+        if (st == ST_OK) {
+            res->n_out = total;
+            if (total > out_cap) res->status = ST_ECAPACITY;
+        }
+    }
+}
+
+void launch_scan_tiles(uint32_t* tile_count, uint32_t n_tiles, Scalars* sc, int32_t* status, void* res,
+                       uint64_t out_cap, hipStream_t stream) {
+    (void)status;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, stream, tile_count, n_tiles, sc, (ResultDev*)res,
+                       out_cap);
+}
+
+// ------------------------------------------------------------------ outlier scatter
+
+__global__ __launch_bounds__(256) void k_scatter(const uint4* __restrict__ stage, uint32_t cap,
+                                                 const Scalars* sc, const int32_t* status,
+                                                 const uint32_t* __restrict__ tile_offset,
+                                                 const uint32_t* __restrict__ block_info, Geom g,
+                                                 uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
+    if (load_status(status) != ST_OK) return;
+    const uint32_t n = min(sc->stage_count, cap);
+    // status OK means every outlier was staged (count <= cap); positions are
+    // checked against the count all the same
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint4 e = stage[i];
+        const uint32_t b = e.z;
+        const uint32_t bx = b % g.nbx;
+        const uint32_t rest = b / g.nbx;
+        const uint32_t by = rest % g.nby;
+        const uint32_t bz = rest / g.nby;
+        const uint32_t t = (bz * g.nby + by) * g.ntx + bx / g.bpt;
+        const uint32_t info = block_info[b];
+        uint32_t pos = tile_offset[t] + (info & ~kOriginFlag);
+        if (!(e.w & kOriginFlag)) pos += (info >> 31) + e.w;
+        if (pos < n) {
+            out_idx[pos] = e.x;
+            out_val[pos] = (int32_t)e.y;
+        }
+    }
+}
+
+void launch_scatter(const uint4* stage, uint32_t stage_cap, const Scalars* sc, const int32_t* status,
+                    const uint32_t* tile_offset, const uint32_t* block_info, Geom g, uint32_t* out_idx,
+                    int32_t* out_val, hipStream_t stream) {
+    uint32_t blocks = (stage_cap + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, stream, stage, stage_cap, sc, status,
+                       tile_offset, block_info, g, out_idx, out_val);
+}
+
+// ------------------------------------------------------------------ decompress
+
+__global__ void k_decompress_init(ResultDev* res, unsigned long long n_out, double eb) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    res->status = ST_OK;
+    res->reserved = 0;
+    res->n_out = n_out;
+    res->eb_abs = eb;
+}
+
+void launch_decompress_init(void* res, uint64_t n_out, double eb, hipStream_t stream) {
+    hipLaunchKernelGGL(k_decompress_init, dim3(1), dim3(64), 0, stream, (ResultDev*)res,
+                       (unsigned long long)n_out, eb);
+}
+
+struct IndexGeom {
+    Geom g;
+    uint32_t lb;   // log2 B
+    uint32_t dim;
+};
+
+__device__ __forceinline__ void cell_block(const IndexGeom& ig, uint32_t idx, uint32_t& bid, uint32_t& local) {
+    const uint32_t x = idx % ig.g.nx;
+    const uint32_t rest = idx / ig.g.nx;
+    const uint32_t y = rest % ig.g.ny;
+    const uint32_t z = rest / ig.g.ny;
+    bid = ((z >> ig.lb) * ig.g.nby + (y >> ig.lb)) * ig.g.nbx + (x >> ig.lb);
+    const uint32_t m = (1u << ig.lb) - 1u;
+    local = (((z & m) << ig.lb | (y & m)) << ig.lb) | (x & m);
+}
+
+// block_start[b] = first outlier of block b or later (b = 0..n_blocks);
+// outliers must be in strictly increasing (block, local row-major) order.
+__global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_idx, uint32_t n_out,
+                                               IndexGeom ig, uint32_t* __restrict__ block_start,
+                                               int32_t* status) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t N = ig.g.N;
+    if (i < n_out) {
+        const uint32_t idx = out_idx[i];
+        bool ok = idx < N;
+        if (ok && i > 0) {
+            const uint32_t prev = out_idx[i - 1];
+            if (prev >= N) {
+                ok = false;
+            } else {
+                uint32_t b0, l0, b1, l1;
+                cell_block(ig, prev, b0, l0);
+                cell_block(ig, idx, b1, l1);
+                ok = (b0 < b1) || (b0 == b1 && l0 < l1);
+            }
+        }
+        if (!ok) store_status(status, ST_ECORRUPT);
+    }
+    if (i <= ig.g.nblocks) {
+        uint32_t lo = 0, hi = n_out;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            const uint32_t idx = out_idx[mid];
+            uint32_t b = 0xffffffffu, l;
+            if (idx < N) cell_block(ig, idx, b, l);
+            if (b < i) lo = mid + 1;
+            else hi = mid;
+        }
+        block_start[i] = lo;
+    }
+}
+
+void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
+                  uint32_t* block_start, int32_t* status, hipStream_t stream) {
+    IndexGeom ig{g, (uint32_t)block_log2, (uint32_t)dim};
+    const uint64_t work = n_out > (uint64_t)g.nblocks + 1 ? (uint64_t)n_out : (uint64_t)g.nblocks + 1;
+    const uint32_t blocks = (uint32_t)((work + 255) / 256);
+    hipLaunchKernelGGL(k_index, dim3(blocks), dim3(256), 0, stream, out_idx, n_out, ig, block_start, status);
+}
+
+}  // namespace dq

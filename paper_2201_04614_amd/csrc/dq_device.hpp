@@ -1,0 +1,326 @@
+// dq_device.hpp - shared device helpers of libdq (gfx950, wave64).
+//
+// Tiling. The field is cut into cubic blocks of edge B (Section III-A: SZ
+// compresses fixed-size blocks independently). A wave owns a "tile": a run of
+// consecutive blocks along x inside one block row (fixed block indices along
+// y and z), so a tile covers a contiguous range of block ids. Lanes span x:
+// lane l holds V consecutive x cells, the wave covers CX = 64*V cells of one
+// grid row per step, and a block row segment is GPB = B/V lanes wide. The
+// wave walks the block's rows (y, then z) in local row-major order, carrying
+// the previous row (and, in 3-D, the previous plane) in registers, so every
+// grid row is read once with fully coalesced 4V-byte loads and the codes are
+// written with 2V-byte stores. When B > CX (1-D only) a block spans several
+// steps and the x neighbour of lane 0 is carried across steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dq {
+
+constexpr int kWaves = 4;                 // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kStageCap = 256;            // LDS outlier staging entries per wave
+constexpr uint32_t kOriginFlag = 0x80000000u;
+constexpr int kTileTarget = 4096;         // minimum cells per tile
+
+constexpr int ST_OK = 0, ST_EINVAL = -1, ST_ERANGE = -2, ST_ECAPACITY = -3, ST_ECORRUPT = -6;
+constexpr int PAD_ZERO = 0, PAD_BLOCK = 1, PAD_EDGE = 2, PAD_GLOBAL = 3;
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <int DIM, int B, int V>
+struct Cfg {
+    static constexpr int CX = 64 * V;                       // cells per wave step
+    static constexpr bool WIDE = B > CX;                    // block spans steps (1-D)
+    static constexpr int GPB = WIDE ? 64 : B / V;           // lanes per block row
+    static constexpr int BPC = WIDE ? 1 : CX / B;           // blocks per step
+    static constexpr int NCH = WIDE ? B / CX : 1;           // steps per block row
+    static constexpr int BY = DIM >= 2 ? B : 1;
+    static constexpr int BZ = DIM == 3 ? B : 1;
+    static constexpr int XCH = WIDE ? 1 : cmax(1, kTileTarget / (CX * BY * BZ));
+    static constexpr int BPT = WIDE ? cmax(1, kTileTarget / B) : XCH * BPC;  // blocks per tile
+    static_assert(V == 1 || V == 2 || V == 4, "V");
+    static_assert(V <= B, "V <= B");
+    static_assert(!WIDE || DIM == 1, "only 1-D blocks may be wider than a wave step");
+    static_assert(DIM < 3 || B * V <= 64, "3-D plane carry must fit in registers");
+};
+
+// Field geometry (x fastest). Unused axes have extent 1 and one block.
+struct Geom {
+    uint32_t nx, ny, nz;
+    uint32_t nbx, nby, nbz;
+    uint32_t ntx;      // tiles per block row
+    uint32_t bpt;      // blocks per tile along x
+    uint32_t n_tiles;
+    uint32_t nblocks;
+    uint64_t N;
+};
+
+// Device scalars of one compress call (at the start of the workspace).
+struct Scalars {
+    double eb;             // absolute error bound
+    double twoeb;          // 2 eb
+    double r;              // fp64 reciprocal of 2 eb (first estimate only)
+    double rel;            // relative factor (REL mode)
+    unsigned long long sumq;   // int64 sum of q, two's complement (GLOBAL pad)
+    unsigned int stage_count;  // outliers staged so far
+    unsigned int kmin, kmax;   // order-preserving keys of min(x), max(x)
+    unsigned int nonfinite;
+    int gpad;                  // global pad value
+    int pad_;
+};
+
+struct EncArgs {
+    const float* x;
+    uint16_t* codes;
+    int32_t* pads;
+    uint32_t* block_info;  // per block: outliers of earlier blocks in the tile | origin flag
+    uint32_t* tile_count;  // per tile: outliers in the tile
+    uint4* stage;          // (index, delta, block, rank | origin flag)
+    uint32_t stage_cap;
+    Scalars* sc;
+    int32_t* status;       // dq_result.status
+    Geom g;
+    int32_t R;
+    int32_t pad_mode;
+};
+
+struct DecArgs {
+    const uint16_t* codes;
+    const uint32_t* out_idx;
+    const int32_t* out_val;
+    const int32_t* pads;
+    const uint32_t* block_start;  // n_blocks + 1 entries (unused when n_out == 0)
+    float* x_hat;
+    int32_t* status;
+    Geom g;
+    double twoeb;
+    uint32_t n_out;
+    int32_t R;
+    int32_t pad_mode;
+};
+
+// ------------------------------------------------------------------ lanes
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m in lanes below this lane
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
+
+// value of lane-1 (lane 0 receives 0): DPP wave_shr:1
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Inclusive prefix sum of v over aligned segments of G lanes (G power of 2).
+template <int G>
+__device__ __forceinline__ uint32_t seg_scan_incl(uint32_t v, int lane) {
+    if constexpr (G >= 2) {
+        uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+        v += ((lane & (G - 1)) >= 1) ? t : 0u;
+    }
+    if constexpr (G >= 4) {
+        uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+        v += ((lane & (G - 1)) >= 2) ? t : 0u;
+    }
+    if constexpr (G >= 8) {
+        uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);  // row_shr:4
+        v += ((lane & (G - 1)) >= 4) ? t : 0u;
+    }
+    if constexpr (G >= 16) {
+        uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);  // row_shr:8
+        v += ((lane & 15) >= 8) ? t : 0u;
+    }
+    if constexpr (G >= 32) {
+        // lane 15 of rows 0 and 2 -> rows 1 and 3
+        uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+        v += t;
+    }
+    if constexpr (G >= 64) {
+        // lane 31 -> rows 2 and 3
+        uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+        v += t;
+    }
+    return v;
+}
+
+// Sum over aligned groups of G lanes (every lane of a group gets the sum).
+template <int G>
+__device__ __forceinline__ long long group_sum64(long long v) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Inclusive prefix sum over the whole wave (rare paths only).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ arithmetic
+
+// Nearest integer to S / n (n > 0), exact halves toward +infinity.
+__device__ __forceinline__ int32_t round_mean(long long S, long long n) {
+    long long q = S / n;
+    long long rm = S - q * n;
+    if (rm < 0) {
+        q -= 1;
+        rm += n;
+    }
+    return (int32_t)(q + ((2 * rm >= n) ? 1 : 0));
+}
+
+// Effective padding of a block: sum over non-empty axis sets S of
+// (-1)^(|S|+1) * halo(S). Constant halos give the pad itself; EDGE halos use
+// the per-axis values e[a] and rounded means for cells in front along
+// several axes.
+template <int DIM>
+__device__ __forceinline__ uint32_t edge_effective(const int32_t* e) {
+    if constexpr (DIM == 1) {
+        return (uint32_t)e[0];
+    } else if constexpr (DIM == 2) {
+        long long s = (long long)e[0] + e[1];
+        return (uint32_t)(s - round_mean(s, 2));
+    } else {
+        long long s01 = (long long)e[0] + e[1], s02 = (long long)e[0] + e[2], s12 = (long long)e[1] + e[2];
+        long long s = s01 + e[2];
+        long long v = s - round_mean(s01, 2) - round_mean(s02, 2) - round_mean(s12, 2) + round_mean(s, 3);
+        return (uint32_t)v;
+    }
+}
+
+// Pre-quantisation (Section III-A): q = nearest integer to x / (2 eb), exact
+// halves to even. Fast path: k = rint(x * r) with r = fl(1 / (2 eb)); k is
+// exact unless x*r lies within 2^-16 of a half-integer (its error is below
+// 2^-18 while |x*r| < 2^32). Near halves the exact residual e = x - 2 eb k is
+// obtained with one fma (its comparison with +-eb is exact) and k is moved by
+// one if needed. The caller runs the slow path for the whole wave when any
+// lane needs it.
+constexpr double kNearHalf = 0.5 - 1.52587890625e-05;  // 0.5 - 2^-16
+constexpr double kQMax = 2147483647.0;
+
+__device__ __forceinline__ double exact_round(float x, double k, double twoeb, double eb) {
+    const double e = __builtin_fma(-twoeb, k, (double)x);
+    if (e > eb) return k + 1.0;
+    if (e < -eb) return k - 1.0;
+    if (e == eb || e == -eb) {
+        const double h = k * 0.5;
+        if (h != __builtin_rint(h)) return e > 0.0 ? k + 1.0 : k - 1.0;  // odd: go to the even side
+    }
+    return k;
+}
+
+template <int V>
+__device__ __forceinline__ void prequant(const float (&x)[V], double r, double twoeb, double eb,
+                                         uint32_t (&q)[V], bool& bad) {
+    double k[V];
+    bool nh = false;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        const double v = (double)x[j] * r;
+        k[j] = __builtin_rint(v);
+        nh |= __builtin_fabs(v - k[j]) > kNearHalf;
+    }
+    if (__builtin_expect(ballot(nh) != 0, 0)) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) k[j] = exact_round(x[j], k[j], twoeb, eb);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        bad |= !(__builtin_fabs(k[j]) <= kQMax);
+        q[j] = (uint32_t)(int32_t)k[j];
+    }
+}
+
+// ------------------------------------------------------------------ vector memory
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int V>
+__device__ __forceinline__ void load_f(const float* p, float (&v)[V]) {
+    if constexpr (V == 1) {
+        v[0] = __builtin_nontemporal_load(p);
+    } else if constexpr (V == 2) {
+        f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_f(float* p, const float (&v)[V]) {
+    if constexpr (V == 1) {
+        __builtin_nontemporal_store(v[0], p);
+    } else if constexpr (V == 2) {
+        f32x2 t = {v[0], v[1]};
+        __builtin_nontemporal_store(t, reinterpret_cast<f32x2*>(p));
+    } else {
+        f32x4 t = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p));
+    }
+}
+
+// V uint16 codes, packed in 16-bit halves of 32-bit words
+template <int V>
+__device__ __forceinline__ void store_codes(uint16_t* p, const uint32_t (&c)[V]) {
+    if constexpr (V == 1) {
+        __builtin_nontemporal_store((uint16_t)c[0], p);
+    } else if constexpr (V == 2) {
+        __builtin_nontemporal_store(c[0] | (c[1] << 16), reinterpret_cast<uint32_t*>(p));
+    } else {
+        u32x2 w = {c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(p));
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void load_codes(const uint16_t* p, uint32_t (&c)[V]) {
+    if constexpr (V == 1) {
+        c[0] = __builtin_nontemporal_load(p);
+    } else if constexpr (V == 2) {
+        uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+        c[0] = w & 0xffffu; c[1] = w >> 16;
+    } else {
+        u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+        c[0] = w.x & 0xffffu; c[1] = w.x >> 16; c[2] = w.y & 0xffffu; c[3] = w.y >> 16;
+    }
+}
+
+// Write a wave's staged outliers (LDS) to the global staging list.
+__device__ __forceinline__ void flush_stage(uint4* sbuf, uint32_t n, uint4* stage, uint32_t cap,
+                                            unsigned int* counter, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, n);
+    base = readlane(base, 0);
+    for (uint32_t i = (uint32_t)lane; i < n; i += 64) {
+        if (base + i < cap) stage[base + i] = sbuf[i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace dq

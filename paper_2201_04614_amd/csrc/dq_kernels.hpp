@@ -1,0 +1,57 @@
+// dq_kernels.hpp - kernel configurations and launchers of libdq.
+#pragma once
+
+#include "dq_device.hpp"
+
+// Every (ndim, B, V) the encode/decode kernels are built for. V is the number
+// of consecutive x cells per lane (vector width of the loads); the host picks
+// the widest V that divides the row length and matches buffer alignment.
+//   1-D: B = 1..4096, V <= B
+//   2-D: B = 1..256,  V <= B, B <= 64 V (a block row fits one wave step)
+//   3-D: B = 1..64,   V <= B, B <= 64 V, B V <= 64 (plane carry in registers)
+#define DQ_CONFIGS(X)                                                            \
+    X(1, 1, 1) X(1, 2, 1) X(1, 2, 2) X(1, 4, 1) X(1, 4, 2) X(1, 4, 4)              \
+    X(1, 8, 1) X(1, 8, 2) X(1, 8, 4) X(1, 16, 1) X(1, 16, 2) X(1, 16, 4)          \
+    X(1, 32, 1) X(1, 32, 2) X(1, 32, 4) X(1, 64, 1) X(1, 64, 2) X(1, 64, 4)       \
+    X(1, 128, 1) X(1, 128, 2) X(1, 128, 4) X(1, 256, 1) X(1, 256, 2) X(1, 256, 4) \
+    X(1, 512, 1) X(1, 512, 2) X(1, 512, 4) X(1, 1024, 1) X(1, 1024, 2)            \
+    X(1, 1024, 4) X(1, 2048, 1) X(1, 2048, 2) X(1, 2048, 4) X(1, 4096, 1)         \
+    X(1, 4096, 2) X(1, 4096, 4)                                                  \
+    X(2, 1, 1) X(2, 2, 1) X(2, 2, 2) X(2, 4, 1) X(2, 4, 2) X(2, 4, 4)              \
+    X(2, 8, 1) X(2, 8, 2) X(2, 8, 4) X(2, 16, 1) X(2, 16, 2) X(2, 16, 4)          \
+    X(2, 32, 1) X(2, 32, 2) X(2, 32, 4) X(2, 64, 1) X(2, 64, 2) X(2, 64, 4)       \
+    X(2, 128, 2) X(2, 128, 4) X(2, 256, 4)                                       \
+    X(3, 1, 1) X(3, 2, 1) X(3, 2, 2) X(3, 4, 1) X(3, 4, 2) X(3, 4, 4)              \
+    X(3, 8, 1) X(3, 8, 2) X(3, 8, 4) X(3, 16, 1) X(3, 16, 2) X(3, 16, 4)          \
+    X(3, 32, 1) X(3, 32, 2) X(3, 64, 1)
+
+namespace dq {
+
+// Returns false when (dim, block, v) is not a built configuration.
+bool launch_encode(int dim, int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
+bool launch_decode(int dim, int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
+// Blocks per tile along x of a configuration (0 if not built).
+int tile_blocks(int dim, int block, int v);
+
+struct AuxArgs {
+    const float* x;
+    Scalars* sc;
+    int32_t* status;
+    uint64_t N;
+};
+
+void launch_compress_init(Scalars* sc, int32_t* status, void* res, double eb, double rel, int eb_mode,
+                          hipStream_t stream);
+void launch_minmax(const AuxArgs& a, hipStream_t stream);
+void launch_resolve_rel(Scalars* sc, int32_t* status, void* res, hipStream_t stream);
+void launch_sumq(const AuxArgs& a, hipStream_t stream);
+void launch_scan_tiles(uint32_t* tile_count, uint32_t n_tiles, Scalars* sc, int32_t* status, void* res,
+                       uint64_t out_cap, hipStream_t stream);
+void launch_scatter(const uint4* stage, uint32_t stage_cap, const Scalars* sc, const int32_t* status,
+                    const uint32_t* tile_offset, const uint32_t* block_info, Geom g, uint32_t* out_idx,
+                    int32_t* out_val, hipStream_t stream);
+void launch_decompress_init(void* res, uint64_t n_out, double eb, hipStream_t stream);
+void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
+                  uint32_t* block_start, int32_t* status, hipStream_t stream);
+
+}  // namespace dq

@@ -1,0 +1,89 @@
+"""C ABI of libdq: loads without a GPU, exports every symbol include/dq.h
+declares, and validates parameters on the host (no compute calls)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2201_04614_amd import binding as dq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(dq.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return dq.lib()
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "dq.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dq_[a-z_]+)\s*\(", text)))
+
+
+def test_header_lists_every_export():
+    assert declared_functions() == sorted(dq.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror(L):
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert dq.strerror(st) and "unknown" not in dq.strerror(st)
+    assert "unknown" in dq.strerror(42)
+
+
+def test_validate_host_only(L):
+    ok = dq.make_params((10, 10), 1e-3, "abs", 4, "zero", 512)
+    assert dq.validate(ok) == dq.DQ_OK
+    bad = [dict(shape=(0, 10)), dict(eb=0.0), dict(eb=float("nan")), dict(eb=1e-320),
+           dict(block=0), dict(pad=7), dict(radius=0), dict(radius=32769), dict(eb_mode=3),
+           dict(shape=(65536, 65536))]
+    base = dict(shape=(10, 10), eb=1e-3, eb_mode="abs", block=4, pad="zero", radius=512)
+    for b in bad:
+        kw = dict(base)
+        kw.update(b)
+        assert dq.validate(dq.make_params(**kw)) == dq.DQ_EINVAL, b
+    p = dq.make_params((1, 1, 1), 1.0)
+    p.ndim = 4
+    assert dq.validate(p) == dq.DQ_EINVAL
+    # valid for the method, outside the GPU kernels' coverage
+    for shape, B in (((100,), 6), ((100,), 8192), ((64, 64), 512), ((8, 8, 8), 128)):
+        assert dq.validate(dq.make_params(shape, 1e-3, "abs", B)) == dq.DQ_ENOTSUP
+    for shape, B in (((100,), 4096), ((64, 64), 256), ((8, 8, 8), 64), ((5, 7, 9), 1)):
+        assert dq.validate(dq.make_params(shape, 1e-3, "abs", B)) == dq.DQ_OK
+
+
+def test_counts_and_workspace(L):
+    p = dq.make_params((20, 33, 17), 1e-3, "rel", 8, "edge_mean", 512)
+    nb = 3 * 5 * 3
+    assert dq.num_blocks(p) == nb
+    assert dq.pad_count(p) == nb * 3
+    for pad, n in (("zero", 0), ("block_mean", nb), ("global_mean", 1)):
+        assert dq.pad_count(dq.make_params((20, 33, 17), 1e-3, "rel", 8, pad)) == n
+    w0 = dq.compress_workspace(p, 0)
+    w1 = dq.compress_workspace(p, 1000)
+    assert w0 > 0 and w1 - w0 >= 16 * 1000
+    assert dq.compress_workspace(p, 10 ** 9) == dq.compress_workspace(p, 20 * 33 * 17)
+    assert dq.decompress_workspace(p) >= 4 * (nb + 1)
+
+
+def test_null_pointers_rejected_before_any_launch(L):
+    p = dq.make_params((64,), 1e-3, "abs", 16, "block_mean", 512)
+    hp = C.byref(p)
+    # x, codes, res, ws missing; pads missing although the mode needs them
+    assert L.dq_compress(hp, None, None, None, None, 0, None, None, None, 0, None, None) == dq.DQ_EINVAL
+    assert L.dq_decompress(hp, 1e-3, None, None, None, 0, None, None, None, None, 0, None,
+                           None) == dq.DQ_EINVAL
+    assert L.dq_decompress(hp, -1.0, None, None, None, 0, None, None, None, None, 0, None,
+                           None) == dq.DQ_EINVAL
+    assert L.dq_result_sync(None, None, None) == dq.DQ_EINVAL

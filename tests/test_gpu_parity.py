@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Codes, outlier indices and values, pads, outlier count, the absolute bound and
+the decoded fp32 values must be bit-identical (all of them are exact integer
+or IEEE results, defined uniquely)."""
+
+import numpy as np
+import pytest
+
+import gpu_util as G
+from paper_2201_04614_amd import binding as dq
+from paper_2201_04614_amd import fields as F
+
+pytestmark = pytest.mark.gpu
+
+PADS = ["zero", "block_mean", "edge_mean", "global_mean"]
+
+
+def test_c1_sinusoid_512(ref):
+    """512x512 sum of 8 sinusoids + noise, abs eb 1e-4 * range, 16x16 blocks,
+    radius 512 (every padding mode)."""
+    x = F.sinusoid_field((512, 512), seed=1)
+    eb = 1e-4 * F.field_range(x)
+    for pad in PADS:
+        G.say(f"c1 pad={pad}")
+        c = G.parity(ref, x, eb, "abs", 16, pad, 512)
+        if pad == "zero":
+            assert c.n_out > 0
+
+
+@pytest.mark.parametrize("offset", [0.0, 2.0])
+def test_c2_grf_small(ref, offset):
+    """k^-3 Gaussian random field, rel eb 1e-3, 8^3 blocks; the offset variant
+    has few near-zero values so zero padding leaves every origin an outlier."""
+    x = F.power_law_grf((64, 64, 64), seed=2)
+    x = x + np.float32(offset * F.field_range(x))
+    for pad in PADS:
+        G.say(f"c2-small offset={offset} pad={pad}")
+        G.parity(ref, x, 1e-3, "rel", 8, pad, 512)
+
+
+def test_c2_grf_full_256(ref):
+    """The 256^3 workload at full size (zero / block-mean / edge-mean)."""
+    x = F.power_law_grf((256, 256, 256), seed=2)
+    for pad in ("zero", "block_mean", "edge_mean"):
+        G.say(f"c2-full pad={pad}")
+        G.parity(ref, x, 1e-3, "rel", 8, pad, 512)
+    xo = x + np.float32(2.0 * F.field_range(x))
+    G.say("c2-full offset zero")
+    c = G.parity(ref, xo, 1e-3, "rel", 8, "zero", 512)
+    assert c.n_out >= 32 ** 3
+
+
+RAGGED = [
+    ((1,), [1, 4]), ((3,), [1, 2, 4]), ((1000,), [1, 2, 8, 16, 256]), ((4099,), [4, 64, 128, 512]),
+    ((12345,), [256, 1024, 4096]), ((1, 1), [1, 2]), ((37, 61), [1, 2, 4, 8, 16, 32]),
+    ((64, 200), [16, 64, 128, 256]), ((300, 9), [4, 8]), ((13, 17, 19), [1, 2, 4, 8, 16]),
+    ((5, 1, 9), [1, 2, 4]), ((33, 40, 44), [8, 16, 32]), ((64, 64, 64), [32, 64]),
+]
+
+
+@pytest.mark.parametrize("shape,blocks", RAGGED, ids=lambda v: str(v))
+def test_ragged_shapes_all_blocks(ref, shape, blocks):
+    x = F.uniform_field(shape, seed=sum(shape), lo=-3.0, hi=5.0)
+    for B in blocks:
+        for pad in PADS:
+            for R, eb in ((512, 2e-3), (2, 0.05)):
+                G.parity(ref, x, eb, "abs", B, pad, R)
+
+
+@pytest.mark.parametrize("shape,B", [((8190,), 16), ((46, 50), 8), ((6, 10, 14), 2), ((7, 9, 11), 4),
+                                     ((10, 30, 62), 8), ((4098,), 1024)])
+def test_vector_widths(ref, shape, B):
+    """Rows whose length is not a multiple of 4, and misaligned base pointers,
+    select the narrower load widths."""
+    import torch
+    x = F.sinusoid_field(shape, seed=3)
+    eb = 1e-3 * F.field_range(x)
+    for pad in PADS:
+        G.parity(ref, x, eb, "abs", B, pad, 256)
+        # the same field starting 4 bytes into an allocation
+        buf = torch.empty(x.size + 1, dtype=torch.float32, device="cuda")
+        buf[1:] = torch.from_numpy(x.ravel()).cuda()
+        G.parity(ref, x, eb, "abs", B, pad, 256, x_dev=buf[1:].view(shape))
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 32768])
+def test_radius_extremes_and_heavy_outliers(ref, R):
+    """R = 1 makes every non-zero residual an outlier: staging overflow paths."""
+    for shape, B in (((70000,), 256), ((200, 300), 16), ((40, 50, 60), 8), ((5000,), 2048)):
+        x = F.uniform_field(shape, seed=R, lo=-100.0, hi=100.0)
+        for pad in ("zero", "edge_mean"):
+            G.parity(ref, x, 1e-4, "abs", B, pad, R)
+
+
+def test_wrapping_extremes(ref):
+    """q near +-(2^31 - 1): residuals wrap modulo 2^32 and still invert exactly."""
+    rng = np.random.default_rng(9)
+    x = rng.choice(np.array([2147483520.0, -2147483520.0, 0.0, 1.0], dtype=np.float32), size=(40, 48))
+    for B in (4, 16):
+        for pad in PADS:
+            G.parity(ref, x, 0.5, "abs", B, pad, 32768)
+
+
+def test_affine_and_constant(ref):
+    for shape, B in (((300,), 16), ((37, 45), 8), ((12, 13, 14), 4)):
+        xa = F.affine_integer_field(shape, -77, (3, -2, 5)[:len(shape)])
+        xc = F.constant_field(shape, 700.0)
+        for pad in PADS:
+            G.parity(ref, xa, 0.5, "abs", B, pad, 512)
+            G.parity(ref, xc, 0.5, "abs", B, pad, 512)
+
+
+def test_exact_halves_round_to_even(ref):
+    """x/(2 eb) exactly k + 1/2: the prequantisation picks the even neighbour."""
+    rng = np.random.default_rng(4)
+    m = rng.integers(-100000, 100000, size=(64, 64))
+    for eb in (0.5, 0.125, 2.0 ** -10):
+        x = ((m + 0.5) * 2 * eb).astype(np.float32)
+        G.parity(ref, x, eb, "abs", 16, "zero", 512)
+    # near-halves with an inexact 2eb
+    x = F.uniform_field((256, 256), 6, -1000.0, 1000.0)
+    G.parity(ref, x, 1e-3, "abs", 16, "block_mean", 512)
+
+
+def test_error_statuses(ref):
+    x = F.uniform_field((50, 60), 1)
+    for v in (np.nan, np.inf):
+        y = x.copy()
+        y[3, 7] = v
+        for mode in ("abs", "rel"):
+            for pad in ("zero", "global_mean"):
+                G.parity(ref, y, 1e-3, mode, 8, pad, 512)
+    y = x.copy()
+    y[10, 10] = 1e7
+    G.parity(ref, y, 1e-3, "abs", 8, "zero", 512)  # ERANGE
+    G.parity(ref, F.constant_field((50, 60), 2.5), 1e-3, "rel", 8, "zero", 512)  # EINVAL
+
+
+def test_capacity(ref):
+    x = F.sinusoid_field((128, 128), seed=4)
+    eb = 1e-5 * F.field_range(x)
+    p = ref.params(x.shape, eb, "abs", 16, "zero", 64)
+    full = ref.compress(p, x)
+    assert full.n_out > 100
+    g = G.gpu_compress(x, eb, "abs", 16, "zero", 64, out_cap=50)
+    assert g["status"] == dq.DQ_ECAPACITY and g["n_out"] == full.n_out
+    assert np.array_equal(g["codes"], full.codes)
+    g0 = G.gpu_compress(x, eb, "abs", 16, "zero", 64, out_cap=0)
+    assert g0["status"] == dq.DQ_ECAPACITY and g0["n_out"] == full.n_out
+
+
+def test_corrupt_streams(ref):
+    x = F.sinusoid_field((64, 64), seed=9)
+    eb = 1e-5 * F.field_range(x)
+    p = ref.params(x.shape, eb, "abs", 8, "block_mean", 32)
+    c = ref.compress(p, x)
+    g = G.gpu_compress(x, eb, "abs", 8, "block_mean", 32)
+    codec = g["codec"]
+
+    def both(codes, idx, val):
+        rs, _ = ref.decompress(p, c.eb_abs, codes, idx, val, c.pads)
+        gs, _ = G.gpu_decompress(codec, c.eb_abs, codes, idx, val, c.pads)
+        return rs, gs
+
+    assert both(c.codes, c.out_idx, c.out_val) == (0, 0)
+    assert both(c.codes, c.out_idx[1:], c.out_val[1:]) == (dq.DQ_ECORRUPT,) * 2
+    sw = c.out_idx.copy()
+    sw[[3, 4]] = sw[[4, 3]]
+    assert both(c.codes, sw, c.out_val) == (dq.DQ_ECORRUPT,) * 2
+    oob = c.out_idx.copy()
+    oob[-1] = x.size
+    assert both(c.codes, oob, c.out_val) == (dq.DQ_ECORRUPT,) * 2
+    nz = int(np.flatnonzero(c.codes.ravel())[0])
+    idx2 = np.sort(np.append(c.out_idx, nz))
+    assert both(c.codes, idx2, np.append(c.out_val, 0)) == (dq.DQ_ECORRUPT,) * 2
+
+
+def test_determinism(ref):
+    x = F.power_law_grf((48, 64, 80), seed=12) + np.float32(3.0)
+    a = G.gpu_compress(x, 1e-4, "rel", 8, "edge_mean", 64)
+    b = G.gpu_compress(x, 1e-4, "rel", 8, "edge_mean", 64)
+    for k in ("codes", "out_idx", "out_val", "pads"):
+        assert np.array_equal(a[k], b[k])
+    assert a["n_out"] == b["n_out"] > 0
