@@ -1,0 +1,200 @@
+"""Benchmark of the dual-quantisation hot path on one MI355X.
+
+Workload (one step): the 256^3 fp32 Gaussian random field with a k^-3 power
+spectrum (seed 2), relative error bound 1e-3, 8^3 blocks, radius 512, run
+through compress + decompress once per padding mode (zero, block mean, edge
+mean) - every stage of the path: value-range pass and bound resolution,
+prequantisation + Lorenzo + codes + outlier staging, outlier scan/scatter,
+outlier index, prefix-sum decode + dequantisation.
+
+Every call reads and writes its own buffers: inputs and outputs rotate over
+enough distinct sets that the working set (> 2 GiB) cannot stay in the 256 MB
+Infinity Cache, so the figure is HBM throughput. Inputs are resident in HBM
+before the timed region.
+
+Prints one JSON line: value = 3 * 4N bytes / step time (GB/s of fp32 input
+through compress + decompress), the roofline of the dominant kernel (timed
+with HIP events recorded around it inside the timed region), and the CPU
+oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+PADS = ("zero", "block_mean", "edge_mean")
+SHAPE = (256, 256, 256)
+EB_REL, BLOCK, RADIUS, SEED = 1e-3, 8, 512, 2
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(x, reps=1):
+    """The oracle, as it stands, on the same step (3 padding modes)."""
+    from oracle import dqref
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    n = x.size
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for pad in PADS:
+            p = dqref.params(x.shape, EB_REL, "rel", BLOCK, pad, RADIUS)
+            c = dqref.compress(p, x, out_cap=n // 16, nthreads=threads)
+            st, _ = dqref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads, nthreads=threads)
+            assert c.status == 0 and st == 0
+    dt = time.perf_counter() - t0
+    return {"value": round(reps * len(PADS) * 4.0 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} full step(s): 256^3 field, 3 padding modes, compress+decompress, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sets", type=int, default=4, help="rotating buffer sets per padding mode")
+    ap.add_argument("--vec", type=int, default=0, help="cells per lane hint (0 = automatic)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path has no "
+              "multi-GPU code in this build; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_04614_amd import binding as dq
+    from paper_2201_04614_amd import fields
+
+    dev = torch.device("cuda:0")
+    log("bench: generating 256^3 k^-3 field")
+    x = fields.power_law_grf(SHAPE, slope=3.0, seed=SEED)
+    n = x.size
+    xs = [[torch.from_numpy(x).to(dev) for _ in range(args.sets)] for _ in PADS]
+    codecs = [[dq.Codec(SHAPE, EB_REL, "rel", BLOCK, pad, RADIUS, out_cap=n // 16, device=dev, vec=args.vec)
+               for _ in range(args.sets)] for pad in PADS]
+    torch.cuda.synchronize()
+
+    # warmup: also fixes each mode's outlier count and bound (identical every step)
+    n_out, eb_abs = {}, {}
+    for w in range(max(1, args.warmup)):
+        for pi, pad in enumerate(PADS):
+            for s in range(args.sets):
+                cd = codecs[pi][s]
+                cd.compress_async(xs[pi][s])
+                r = cd.result()
+                assert r.status == dq.DQ_OK, dq.strerror(r.status)
+                n_out[pad], eb_abs[pad] = int(r.n_out), float(r.eb_abs)
+                cd.decompress_async(eb_abs[pad], n_out[pad])
+                rd = cd.decompress_result()
+                assert rd.status == dq.DQ_OK, dq.strerror(rd.status)
+    torch.cuda.synchronize()
+    log(f"bench: warmup done, outliers per mode {n_out}")
+
+    def run_steps(hooks=None):
+        for k in range(args.steps):
+            s = k % args.sets
+            for pi, pad in enumerate(PADS):
+                cd = codecs[pi][s]
+                he, hd = hooks[k][pi] if hooks else (None, None)
+                cd.compress_async(xs[pi][s], hooks=he)
+                cd.decompress_async(eb_abs[pad], n_out[pad], hooks=hd)
+
+    # timed region: K steps, every kernel enqueued back to back on one stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    run_steps()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"bench: {args.steps} steps, {ms_step:.4f} ms/step")
+
+    # per-kernel durations: the same K steps again with HIP events recorded
+    # right before and after each encode and decode launch (event records
+    # add gaps between kernels, so this pass is kept out of the step time)
+    hooks = [[(dq.Hook(), dq.Hook()) for _ in PADS] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    run_steps(hooks)
+    torch.cuda.synchronize()
+
+    # the timed results are the warmup's: same field, same outliers
+    for pi, pad in enumerate(PADS):
+        for s in range(args.sets):
+            r = codecs[pi][s].result()
+            assert r.status == dq.DQ_OK and int(r.n_out) == n_out[pad]
+            assert codecs[pi][s].decompress_result().status == dq.DQ_OK
+
+    enc_ms = {pad: np.mean([hooks[k][pi][0].elapsed_ms() for k in range(args.steps)])
+              for pi, pad in enumerate(PADS)}
+    dec_ms = {pad: np.mean([hooks[k][pi][1].elapsed_ms() for k in range(args.steps)])
+              for pi, pad in enumerate(PADS)}
+    for row in hooks:
+        for he, hd in row:
+            he.close()
+            hd.close()
+
+    nb = dq.num_blocks(codecs[0][0].p)
+    pads_bytes = {"zero": 0, "block_mean": 4 * nb, "edge_mean": 12 * nb}
+    # algorithmic bytes per launch: encode reads x, writes codes, outliers
+    # (index + value) and pads; decode reads the same stream and writes x_hat
+    enc_bytes = {pad: 6.0 * n + 8.0 * n_out[pad] + pads_bytes[pad] for pad in PADS}
+    dec_bytes = {pad: 6.0 * n + 8.0 * n_out[pad] + pads_bytes[pad] for pad in PADS}
+    enc_tot, dec_tot = sum(enc_ms.values()), sum(dec_ms.values())
+    if enc_tot >= dec_tot:
+        kname, kms, kbytes = "encode", enc_tot / len(PADS), np.mean(list(enc_bytes.values()))
+    else:
+        kname, kms, kbytes = "decode", dec_tot / len(PADS), np.mean(list(dec_bytes.values()))
+    achieved = kbytes / (kms * 1e-3) / 1e9
+
+    value = len(PADS) * 4.0 * n / (ms_step * 1e-3) / 1e9
+    # bytes the whole step must move: value-range pass (4N) + encode + decode per mode
+    step_bytes = sum(4.0 * n + enc_bytes[p] + dec_bytes[p] for p in PADS)
+    out = {
+        "metric": "dual-quant compress+decompress GB/s on 1 MI355X; % HBM peak; outlier %",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+i32",
+        "data": "synthetic",
+        "config": {"workload": "256^3 fp32 k^-3 Gaussian random field (seed 2), rel eb 1e-3, "
+                               "8^3 blocks, radius 512, padding zero/block_mean/edge_mean; "
+                               "step = compress+decompress per mode",
+                   "shape": list(SHAPE), "block": BLOCK, "radius": RADIUS, "eb_rel": EB_REL,
+                   "buffer_sets": args.sets, "vec_hint": args.vec},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "avg_kernel_ms": round(kms, 5)},
+        "kernels_ms": {"encode": {p: round(v, 5) for p, v in enc_ms.items()},
+                       "decode": {p: round(v, 5) for p, v in dec_ms.items()}},
+        "outlier_pct": {p: round(100.0 * n_out[p] / n, 5) for p in PADS},
+        "n_out": n_out,
+        "eb_abs": eb_abs[PADS[0]],
+        "step_algorithmic_GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "step_pct_hbm_peak": round(100.0 * step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 2),
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(x)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,7 +86,11 @@ typedef enum {
  *  block     block edge B >= 1 (GPU: a power of two, B <= 4096 in 1-D,
  *            B <= 256 in 2-D, B <= 64 in 3-D)
  *  pad_mode  dq_pad_mode
- *  radius    R in [1, 32768]: codes are uint16, 0 marks an outlier */
+ *  radius    R in [1, 32768]: codes are uint16, 0 marks an outlier
+ *  vec       kernel tuning hint, no effect on results: consecutive cells per
+ *            lane (vector length of the loads), 1, 2 or 4; 0 = automatic.
+ *            A hint the field or the buffer alignment does not allow is
+ *            replaced by the automatic choice. */
 typedef struct {
     int32_t ndim;
     int32_t eb_mode;
@@ -95,7 +99,7 @@ typedef struct {
     int32_t block;
     int32_t pad_mode;
     int32_t radius;
-    int32_t reserved; /* set to 0 */
+    int32_t vec;
 } dq_params;
 
 /* Device-resident outcome of one call. */

@@ -35,7 +35,7 @@ class DQError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("eb_mode", C.c_int32), ("shape", C.c_int64 * 3),
                 ("eb", C.c_double), ("block", C.c_int32), ("pad_mode", C.c_int32),
-                ("radius", C.c_int32), ("reserved", C.c_int32)]
+                ("radius", C.c_int32), ("vec", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -89,7 +89,7 @@ def strerror(status):
         return f"status {status}"
 
 
-def make_params(shape, eb, eb_mode="abs", block=16, pad="zero", radius=512):
+def make_params(shape, eb, eb_mode="abs", block=16, pad="zero", radius=512, vec=0):
     shape = tuple(int(s) for s in shape)
     p = Params()
     p.ndim = len(shape)
@@ -100,7 +100,7 @@ def make_params(shape, eb, eb_mode="abs", block=16, pad="zero", radius=512):
     p.block = int(block)
     p.pad_mode = PAD_MODES[pad] if isinstance(pad, str) else int(pad)
     p.radius = int(radius)
-    p.reserved = 0
+    p.vec = int(vec)
     return p
 
 
@@ -222,12 +222,12 @@ class Codec:
     field configuration (no allocation per call)."""
 
     def __init__(self, shape, eb, eb_mode="abs", block=16, pad="zero", radius=512,
-                 out_cap=None, device="cuda"):
+                 out_cap=None, device="cuda", vec=0):
         torch = _torch()
         self.shape = tuple(int(s) for s in shape)
         self.n = int(np.prod(self.shape))
         self.block, self.pad, self.radius = int(block), pad, int(radius)
-        self.p = make_params(self.shape, eb, eb_mode, block, pad, radius)
+        self.p = make_params(self.shape, eb, eb_mode, block, pad, radius, vec)
         st = validate(self.p)
         if st != DQ_OK:
             raise DQError(st, "dq_validate")

@@ -40,6 +40,7 @@ dq_status validate(const dq_params* p, bool check_eb) {
     if (p->block < 1) return DQ_EINVAL;
     if (p->pad_mode < DQ_PAD_ZERO || p->pad_mode > DQ_PAD_GLOBAL_MEAN) return DQ_EINVAL;
     if (p->radius < 1 || p->radius > 32768) return DQ_EINVAL;
+    if (p->vec != 0 && p->vec != 1 && p->vec != 2 && p->vec != 4) return DQ_EINVAL;
     // GPU kernel coverage
     const int maxb = p->ndim == 1 ? 4096 : (p->ndim == 2 ? 256 : 64);
     if (!is_pow2(p->block) || p->block > maxb) return DQ_ENOTSUP;
@@ -86,11 +87,28 @@ bool finish_plan(const dq_params* p, int V, Plan& pl) {
 bool make_plan(const dq_params* p, const void* fptr, const void* cptr, Plan& pl) {
     const uintptr_t fa = reinterpret_cast<uintptr_t>(fptr);
     const uintptr_t ca = reinterpret_cast<uintptr_t>(cptr);
+    if (p->vec) {
+        const int V = p->vec;
+        if ((fa % (4u * V)) == 0 && (ca % (2u * V)) == 0 && finish_plan(p, V, pl)) return true;
+    }
+    // Automatic: the widest vector that still gives every SIMD of the chip
+    // (256 CUs x 4) at least two waves; otherwise the one with most tiles.
+    constexpr uint32_t kWaveTarget = 2048;
+    bool found = false;
     for (int V = 4; V >= 1; V >>= 1) {
         if ((fa % (4u * V)) != 0 || (ca % (2u * V)) != 0) continue;
-        if (finish_plan(p, V, pl)) return true;
+        Plan cand;
+        if (!finish_plan(p, V, cand)) continue;
+        if (!found || cand.g.n_tiles > pl.g.n_tiles) {
+            pl = cand;
+            found = true;
+        }
+        if (cand.g.n_tiles >= kWaveTarget) {
+            pl = cand;
+            return true;
+        }
     }
-    return false;
+    return found;
 }
 
 uint64_t max_tiles(const dq_params* p) {
@@ -103,7 +121,7 @@ uint64_t max_tiles(const dq_params* p) {
 }
 
 struct CompressLayout {
-    uint64_t sc, tiles, info, stage, total;
+    uint64_t sc, parts, tiles, info, stage, total;
 };
 
 CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
@@ -112,7 +130,8 @@ CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     const uint64_t cap = out_cap < g.N ? out_cap : g.N;
     CompressLayout L;
     L.sc = 0;
-    L.tiles = align_up(sizeof(Scalars));
+    L.parts = align_up(sizeof(Scalars));
+    L.tiles = L.parts + align_up(sizeof(uint4) * kMinmaxParts);
     L.info = L.tiles + align_up(4 * max_tiles(p));
     L.stage = L.info + align_up(4ull * g.nblocks);
     L.total = L.stage + align_up(16 * cap);
@@ -196,11 +215,13 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     uint4* stage = reinterpret_cast<uint4*>(w + L.stage);
     int32_t* status = &res->status;
 
-    launch_compress_init(sc, status, res, p->eb, p->eb, p->eb_mode, stream);
+    uint4* parts = reinterpret_cast<uint4*>(w + L.parts);
     AuxArgs aa{x, sc, status, pl.g.N};
     if (p->eb_mode == DQ_EB_REL) {
-        launch_minmax(aa, stream);
-        launch_resolve_rel(sc, status, res, stream);
+        const int nparts = launch_minmax(aa, parts, stream);
+        launch_resolve_rel(sc, res, parts, nparts, p->eb, stream);  // also initialises the call
+    } else {
+        launch_compress_init(sc, res, p->eb, stream);
     }
     if (p->pad_mode == DQ_PAD_GLOBAL_MEAN) launch_sumq(aa, stream);
 

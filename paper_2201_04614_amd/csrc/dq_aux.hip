@@ -31,35 +31,27 @@ __device__ __forceinline__ int load_status(const int32_t* status) {
 
 // ------------------------------------------------------------------ compress init
 
-__global__ void k_compress_init(Scalars* sc, ResultDev* res, double eb, double rel, int eb_mode) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void init_scalars(Scalars* sc, ResultDev* res) {
     sc->stage_count = 0;
     sc->sumq = 0;
-    sc->kmin = 0xffffffffu;
-    sc->kmax = 0u;
-    sc->nonfinite = 0;
-    sc->rel = rel;
     sc->gpad = 0;
     res->status = ST_OK;
     res->reserved = 0;
     res->n_out = 0;
-    if (eb_mode == 0) {
-        sc->eb = eb;
-        sc->twoeb = 2.0 * eb;
-        sc->r = 1.0 / (2.0 * eb);
-        res->eb_abs = eb;
-    } else {
-        sc->eb = 0.0;
-        sc->twoeb = 0.0;
-        sc->r = 0.0;
-        res->eb_abs = 0.0;
-    }
 }
 
-void launch_compress_init(Scalars* sc, int32_t* status, void* res, double eb, double rel, int eb_mode,
-                          hipStream_t stream) {
-    (void)status;
-    hipLaunchKernelGGL(k_compress_init, dim3(1), dim3(64), 0, stream, sc, (ResultDev*)res, eb, rel, eb_mode);
+// absolute bound given by the caller
+__global__ void k_compress_init(Scalars* sc, ResultDev* res, double eb) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    init_scalars(sc, res);
+    sc->eb = eb;
+    sc->twoeb = 2.0 * eb;
+    sc->r = 1.0 / (2.0 * eb);
+    res->eb_abs = eb;
+}
+
+void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream) {
+    hipLaunchKernelGGL(k_compress_init, dim3(1), dim3(64), 0, stream, sc, (ResultDev*)res, eb);
 }
 
 // ------------------------------------------------------------------ value range (REL bound)
@@ -74,7 +66,18 @@ __device__ __forceinline__ float funkey(uint32_t k) {
     return __uint_as_float(u);
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N, Scalars* sc, int vec4) {
+__device__ __forceinline__ void minmax_acc(float e, uint32_t& kmin, uint32_t& kmax, bool& nf) {
+    const bool fin = __builtin_isfinite(e);
+    nf |= !fin;
+    const uint32_t k = fkey(e);
+    kmin = fin ? min(kmin, k) : kmin;
+    kmax = fin ? max(kmax, k) : kmax;
+}
+
+// Per-workgroup min / max keys and a non-finite flag (no atomics: the
+// partials are combined by k_resolve_rel).
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N, uint4* parts, int vec4) {
+    __shared__ uint32_t smin[4], smax[4], snf[4];
     uint32_t kmin = 0xffffffffu, kmax = 0u;
     bool nf = false;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,60 +86,104 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
     if (vec4) {
         const uint64_t n4 = N / 4;
         const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
-        for (uint64_t i = tid; i < n4; i += stride) {
-            const f32x4 v = __builtin_nontemporal_load(x4 + i);
-            const float e[4] = {v.x, v.y, v.z, v.w};
+        uint64_t i = tid;
+        for (; i + 3 * stride < n4; i += 4 * stride) {  // four 16-byte loads in flight
+            f32x4 v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bool fin = __builtin_isfinite(e[j]);
-                nf |= !fin;
-                const uint32_t k = fkey(e[j]);
-                kmin = fin ? min(kmin, k) : kmin;
-                kmax = fin ? max(kmax, k) : kmax;
+            for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(x4 + i + u * stride);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                minmax_acc(v[u].x, kmin, kmax, nf);
+                minmax_acc(v[u].y, kmin, kmax, nf);
+                minmax_acc(v[u].z, kmin, kmax, nf);
+                minmax_acc(v[u].w, kmin, kmax, nf);
             }
+        }
+        for (; i < n4; i += stride) {
+            const f32x4 v = __builtin_nontemporal_load(x4 + i);
+            minmax_acc(v.x, kmin, kmax, nf);
+            minmax_acc(v.y, kmin, kmax, nf);
+            minmax_acc(v.z, kmin, kmax, nf);
+            minmax_acc(v.w, kmin, kmax, nf);
         }
         start = n4 * 4;
     }
-    for (uint64_t i = start + tid; i < N; i += stride) {
-        const float e = x[i];
-        const bool fin = __builtin_isfinite(e);
-        nf |= !fin;
-        const uint32_t k = fkey(e);
-        kmin = fin ? min(kmin, k) : kmin;
-        kmax = fin ? max(kmax, k) : kmax;
-    }
+    for (uint64_t i = start + tid; i < N; i += stride) minmax_acc(x[i], kmin, kmax, nf);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
         kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
     }
-    const uint64_t anynf = ballot(nf);
+    const bool anynf = ballot(nf) != 0;
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(&sc->kmin, kmin);
-        atomicMax(&sc->kmax, kmax);
-        if (anynf) atomicOr(&sc->nonfinite, 1u);
+        smin[wave] = kmin;
+        smax[wave] = kmax;
+        snf[wave] = anynf ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint4 pr = make_uint4(smin[0], smax[0], snf[0], 0u);
+        for (int w = 1; w < 4; ++w) {
+            pr.x = min(pr.x, smin[w]);
+            pr.y = max(pr.y, smax[w]);
+            pr.z |= snf[w];
+        }
+        parts[blockIdx.x] = pr;
     }
 }
 
-void launch_minmax(const AuxArgs& a, hipStream_t stream) {
+int launch_minmax(const AuxArgs& a, uint4* parts, hipStream_t stream) {
     const int vec4 = ((reinterpret_cast<uintptr_t>(a.x) & 15u) == 0) ? 1 : 0;
     uint64_t work = vec4 ? a.N / 4 : a.N;
-    uint64_t blocks = (work + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    uint64_t blocks = (work + 1023) / 1024;
+    if (blocks > kMinmaxParts) blocks = kMinmaxParts;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_minmax, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, vec4);
+    hipLaunchKernelGGL(k_minmax, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, parts, vec4);
+    return (int)blocks;
 }
 
-// Relative bound (Section II-B, value-range relative): eb = rel * (max - min).
-__global__ void k_resolve_rel(Scalars* sc, ResultDev* res) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (sc->nonfinite) {
+// Initialises the call's scalars and resolves the relative bound
+// (Section II-B, value-range relative): eb = rel * (max - min).
+__global__ __launch_bounds__(1024) void k_resolve_rel(Scalars* sc, ResultDev* res, const uint4* parts,
+                                                      int nparts, double rel) {
+    __shared__ uint32_t smin[16], smax[16], snf[16];
+    uint32_t kmin = 0xffffffffu, kmax = 0u, nf = 0u;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        const uint4 pr = parts[i];
+        kmin = min(kmin, pr.x);
+        kmax = max(kmax, pr.y);
+        nf |= pr.z;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+        nf |= (uint32_t)__shfl_xor((int)nf, off);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smin[wave] = kmin;
+        smax[wave] = kmax;
+        snf[wave] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+        kmin = min(kmin, smin[w]);
+        kmax = max(kmax, smax[w]);
+        nf |= snf[w];
+    }
+    init_scalars(sc, res);
+    sc->eb = sc->twoeb = sc->r = 0.0;
+    res->eb_abs = 0.0;
+    if (nf) {
         res->status = ST_ERANGE;
         return;
     }
-    const double mn = (double)funkey(sc->kmin);
-    const double mx = (double)funkey(sc->kmax);
-    const double eb = sc->rel * (mx - mn);
+    const double mn = (double)funkey(kmin);
+    const double mx = (double)funkey(kmax);
+    const double eb = rel * (mx - mn);
     const double r = 1.0 / (2.0 * eb);
     if (!(eb > 0.0) || !__builtin_isfinite(eb) || !__builtin_isfinite(r)) {
         res->status = ST_EINVAL;
@@ -148,19 +195,20 @@ __global__ void k_resolve_rel(Scalars* sc, ResultDev* res) {
     res->eb_abs = eb;
 }
 
-void launch_resolve_rel(Scalars* sc, int32_t* status, void* res, hipStream_t stream) {
-    (void)status;
-    hipLaunchKernelGGL(k_resolve_rel, dim3(1), dim3(64), 0, stream, sc, (ResultDev*)res);
+void launch_resolve_rel(Scalars* sc, void* res, const uint4* parts, int nparts, double rel, hipStream_t stream) {
+    hipLaunchKernelGGL(k_resolve_rel, dim3(1), dim3(1024), 0, stream, sc, (ResultDev*)res, parts, nparts, rel);
 }
 
 // ------------------------------------------------------------------ global mean of q
 
 __global__ __launch_bounds__(256) void k_sumq(const float* __restrict__ x, uint64_t N, Scalars* sc,
                                               int32_t* status) {
+    __shared__ long long ssum[4];
+    __shared__ int sbad[4];
     if (load_status(status) != ST_OK) return;
     const double r = sc->r, twoeb = sc->twoeb, eb = sc->eb;
     long long s = 0;
-    bool bad = false;
+    uint64_t bad = 0;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     // uniform trip count so the wave-wide near-half check in prequant sees all lanes
@@ -174,16 +222,23 @@ __global__ __launch_bounds__(256) void k_sumq(const float* __restrict__ x, uint6
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    const uint64_t anybad = ballot(bad);
+    const bool anybad = bad != 0;
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&sc->sumq, (unsigned long long)s);
-        if (anybad) store_status(status, ST_ERANGE);
+        ssum[wave] = s;
+        sbad[wave] = anybad ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = ssum[0] + ssum[1] + ssum[2] + ssum[3];
+        atomicAdd(&sc->sumq, (unsigned long long)t);  // one atomic per workgroup
+        if (sbad[0] | sbad[1] | sbad[2] | sbad[3]) store_status(status, ST_ERANGE);
     }
 }
 
 void launch_sumq(const AuxArgs& a, hipStream_t stream) {
-    uint64_t blocks = (a.N + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    uint64_t blocks = (a.N + 1023) / 1024;
+    if (blocks > 512) blocks = 512;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_sumq, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, a.status);
 }

@@ -5,11 +5,12 @@
 // axis, so its inverse inside a block is the n-D inclusive prefix sum; the
 // padding enters only through the block origin, so
 //     q(u) = P_eff + sum_{w <= u, same block} delta(w).
-// Per tile and row: load V uint16 codes per lane, delta = code - R (or the
-// outlier value, looked up by its rank inside the block), in-lane prefix over
-// the V cells, segmented DPP scan over the GPB lanes of each block row,
-// running sums over rows (y) and planes (z) in registers, add P_eff, and
-// dequantise x_hat = (float)((double)q * 2eb) with one fp64 product.
+// Per tile: load a batch of rows of uint16 codes (V per lane, all loads in
+// flight before the first use); delta = code - R, or the outlier value looked
+// up by its rank inside the block; in-lane prefix over the V cells, segmented
+// DPP scan over the GPB lanes of each block row, running sums over rows (y)
+// and planes (z) in registers, add P_eff, and dequantise
+// x_hat = (float)((double)q * 2eb) with one fp64 product.
 #include "dq_device.hpp"
 #include "dq_kernels.hpp"
 
@@ -27,6 +28,164 @@ __device__ __forceinline__ uint32_t block_peff(const DecArgs& a, uint32_t blk) {
     return edge_effective<DIM>(e);
 }
 
+template <int DIM, int B, int V>
+struct DecState {
+    uint32_t rank;  // zero codes seen so far in this lane's block
+    uint32_t os, oe;  // outlier run of the block
+    uint32_t peff;
+    uint32_t pY[V];
+    uint32_t pZ[DIM == 3 ? B : 1][V];
+
+    __device__ __forceinline__ void init(const DecArgs& a, uint32_t blk, bool gvalid) {
+        rank = 0;
+        os = oe = 0;
+        if (a.n_out && gvalid) {
+            os = a.block_start[blk];
+            oe = a.block_start[blk + 1];
+        }
+        peff = gvalid ? block_peff<DIM>(a, blk) : 0u;
+#pragma unroll
+        for (int j = 0; j < V; ++j) pY[j] = 0;
+#pragma unroll
+        for (int k = 0; k < (DIM == 3 ? B : 1); ++k)
+#pragma unroll
+            for (int j = 0; j < V; ++j) pZ[k][j] = 0;
+    }
+};
+
+// Replace zero codes of this row by their outliers: the k-th zero code of a
+// block (local row-major order) is the block's k-th outlier.
+template <int V>
+__device__ __forceinline__ void fetch_outliers(const DecArgs& a, const uint32_t (&c)[V], uint32_t (&d)[V],
+                                               uint32_t& rank, uint32_t os, uint32_t oe, uint64_t gmask,
+                                               uint64_t gbase, bool& corrupt) {
+    bool anyzero = false;
+#pragma unroll
+    for (int j = 0; j < V; ++j) anyzero = anyzero || c[j] == 0u;
+    if (ballot(anyzero)) {  // rare: entered by the whole wave
+        uint64_t m[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) m[j] = ballot(c[j] == 0u);
+        uint32_t below = 0, gtot = 0, own = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            below += mbcnt(m[j] & gmask);
+            gtot += popc(m[j] & gmask);
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (c[j] == 0u) {
+                const uint32_t k = os + rank + below + own;
+                ++own;
+                if (k < oe && a.out_idx[k] == (uint32_t)(gbase + j)) {
+                    d[j] = (uint32_t)a.out_val[k];
+                } else {
+                    corrupt = true;
+                    d[j] = 0;
+                }
+            }
+        }
+        rank += gtot;
+    }
+}
+
+template <int DIM, int B, int V>
+__device__ __forceinline__ void dec_row(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[V], int yl,
+                                        uint64_t row, uint32_t x0, bool xin, uint64_t gmask, int lane,
+                                        bool& corrupt) {
+    using C = Cfg<DIM, B, V>;
+    const uint32_t R = (uint32_t)a.R;
+    uint32_t cc[V], d[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        cc[j] = xin ? c[j] : R;  // lanes past the field edge decode zeros
+        d[j] = cc[j] - R;
+    }
+    fetch_outliers<V>(a, cc, d, st.rank, st.os, st.oe, gmask, row + x0, corrupt);
+    // x: in-lane prefix, then segmented scan across the block row
+    uint32_t s[V];
+    s[0] = d[0];
+#pragma unroll
+    for (int j = 1; j < V; ++j) s[j] = s[j - 1] + d[j];
+    const uint32_t incl = seg_scan_incl<C::GPB>(s[V - 1], lane);
+    const uint32_t excl = incl - s[V - 1];
+    float o[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        uint32_t p = s[j] + excl;
+        if constexpr (DIM >= 2) {
+            p = (yl == 0) ? p : p + st.pY[j];
+            st.pY[j] = p;
+        }
+        if constexpr (DIM == 3) {
+            p = p + st.pZ[yl][j];  // zero on the block's first plane
+            st.pZ[yl][j] = p;
+        }
+        const int32_t q = (int32_t)(p + st.peff);
+        o[j] = (float)((double)q * a.twoeb);
+    }
+    if (xin) store_f<V>(a.x_hat + row + x0, o);
+}
+
+// A batch of NR consecutive rows (local rows yb .. yb+NR-1 of local plane zl)
+// of a 2-D/3-D step: the outlier lookup is entered once per batch by the
+// whole wave, the prefix sums and dequantisation are branch-free across rows.
+template <int DIM, int B, int V, int NR>
+__device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[NR][V],
+                                          int yb, uint32_t z, uint32_t y0, uint32_t x0, bool xin, uint64_t gmask,
+                                          int lane, bool& corrupt) {
+    using C = Cfg<DIM, B, V>;
+    const uint32_t R = (uint32_t)a.R;
+    const uint32_t ny = a.g.ny, nx = a.g.nx;
+    uint32_t d[NR][V];
+    bool anyzero = false;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const uint32_t cc = xin ? c[i][j] : R;  // lanes past the field edge decode zeros
+            d[i][j] = cc - R;
+            anyzero = anyzero || (cc == 0u && y0 + i < ny);
+        }
+    }
+    if (ballot(anyzero)) {  // rare: rows in order, so ranks follow local row-major order
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (y0 + i >= ny) continue;  // uniform
+            uint32_t cc[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) cc[j] = xin ? c[i][j] : R;
+            fetch_outliers<V>(a, cc, d[i], st.rank, st.os, st.oe, gmask, ((uint64_t)z * ny + y0 + i) * nx + x0,
+                              corrupt);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int yl = yb + i;
+        // x: in-lane prefix, then segmented scan across the block row
+        uint32_t s[V];
+        s[0] = d[i][0];
+#pragma unroll
+        for (int j = 1; j < V; ++j) s[j] = s[j - 1] + d[i][j];
+        const uint32_t incl = seg_scan_incl<C::GPB>(s[V - 1], lane);
+        const uint32_t excl = incl - s[V - 1];
+        float o[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            uint32_t p = s[j] + excl;
+            p = (yl == 0) ? p : p + st.pY[j];
+            st.pY[j] = p;
+            if constexpr (DIM == 3) {
+                p = p + st.pZ[yl][j];  // zero on the block's first plane
+                st.pZ[yl][j] = p;
+            }
+            const int32_t q = (int32_t)(p + st.peff);
+            o[j] = (float)((double)q * a.twoeb);
+        }
+        if (xin && y0 + i < ny) store_f<V>(a.x_hat + ((uint64_t)z * ny + y0 + i) * nx + x0, o);
+    }
+}
+
 __device__ __forceinline__ void mark_corrupt(int32_t* status) {
     __hip_atomic_store(status, ST_ECORRUPT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -34,12 +193,10 @@ __device__ __forceinline__ void mark_corrupt(int32_t* status) {
 template <int DIM, int B, int V>
 __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     using C = Cfg<DIM, B, V>;
-    const int wave = threadIdx.x >> 6;
+    const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kWaves + wave;
     if (t >= a.g.n_tiles) return;
-    const uint32_t R = (uint32_t)a.R;
-    const double twoeb = a.twoeb;
     const uint32_t tx = t % a.g.ntx;
     const uint32_t rr = t / a.g.ntx;
     const uint32_t by = rr % a.g.nby;
@@ -52,105 +209,86 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
         const bool leader = gl == 0;
         const uint64_t gmask = (C::GPB == 64) ? ~0ull
                                               : (((1ull << C::GPB) - 1) << (lane & ~(C::GPB - 1)));
-        for (int ch = 0; ch < C::XCH; ++ch) {
-            const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
-            if (bx0 >= a.g.nbx) break;
-            const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
-            const bool gvalid = bx < a.g.nbx;
-            const uint32_t x0 = bx0 * B + (uint32_t)lane * V;
-            const bool xin = x0 < nx;
-            const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
-            uint32_t os = 0, oe = 0;
-            if (a.n_out && gvalid) {
-                os = a.block_start[blk];
-                oe = a.block_start[blk + 1];
-            }
-            const uint32_t peff = gvalid ? block_peff<DIM>(a, blk) : 0u;
-            uint32_t rank = 0;
-            uint32_t pY[V];
-            uint32_t pZ[C::BY][V];
+        if constexpr (DIM == 1) {
+            for (int cb = 0; cb < C::XCH; cb += C::NBR) {
+                if (tx * C::BPT + cb * C::BPC >= a.g.nbx) break;
+                uint32_t c[C::NBR][V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) pY[j] = 0;
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t x0 = (tx * C::BPT + (cb + i) * C::BPC) * B + (uint32_t)lane * V;
+                    load_codes<V>(a.codes + min(x0, nx - V), c[i]);  // clamped: always in bounds
+                }
 #pragma unroll
-            for (int k = 0; k < C::BY; ++k)
-#pragma unroll
-                for (int j = 0; j < V; ++j) pZ[k][j] = 0;
-
-            for (int zl = 0; zl < C::BZ; ++zl) {
-                const uint32_t z = bz * B + zl;
-                if (z >= nz) break;
-#pragma unroll
-                for (int yl = 0; yl < C::BY; ++yl) {
-                    const uint32_t y = by * B + yl;
-                    if (y >= ny) continue;  // uniform: rows past the field edge
-                    const uint64_t row = ((uint64_t)z * ny + y) * nx;
-                    uint32_t c[V];
-                    if (xin) {
-                        load_codes<V>(a.codes + row + x0, c);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < V; ++j) c[j] = R;
-                    }
-                    uint32_t d[V];
-                    uint64_t m[V];
-                    uint64_t any = 0;
-#pragma unroll
-                    for (int j = 0; j < V; ++j) {
-                        d[j] = c[j] - R;
-                        m[j] = ballot(c[j] == 0u);
-                        any |= m[j];
-                    }
-                    if (any) {  // outliers: k-th zero code of a block is its k-th outlier
-                        uint32_t below = 0, gtot = 0, own = 0;
-#pragma unroll
-                        for (int j = 0; j < V; ++j) {
-                            below += mbcnt(m[j] & gmask);
-                            gtot += popc(m[j] & gmask);
-                        }
-#pragma unroll
-                        for (int j = 0; j < V; ++j) {
-                            if (c[j] == 0u) {
-                                const uint32_t k = os + rank + below + own;
-                                ++own;
-                                const uint32_t gi = (uint32_t)(row + x0 + j);
-                                if (k < oe && a.out_idx[k] == gi) {
-                                    d[j] = (uint32_t)a.out_val[k];
-                                } else {
-                                    corrupt = true;
-                                    d[j] = 0;
-                                }
-                            }
-                        }
-                        rank += gtot;
-                    }
-                    // x: in-lane prefix, then segmented scan across the block row
-                    uint32_t s[V];
-                    s[0] = d[0];
-#pragma unroll
-                    for (int j = 1; j < V; ++j) s[j] = s[j - 1] + d[j];
-                    const uint32_t incl = seg_scan_incl<C::GPB>(s[V - 1], lane);
-                    const uint32_t excl = incl - s[V - 1];
-                    float o[V];
-#pragma unroll
-                    for (int j = 0; j < V; ++j) {
-                        uint32_t p = s[j] + excl;
-                        if constexpr (DIM >= 2) {
-                            p = (yl == 0) ? p : p + pY[j];
-                            pY[j] = p;
-                        }
-                        if constexpr (DIM == 3) {
-                            p = p + pZ[yl][j];
-                            pZ[yl][j] = p;
-                        }
-                        const int32_t q = (int32_t)(p + peff);
-                        o[j] = (float)((double)q * twoeb);
-                    }
-                    if (xin) store_f<V>(a.x_hat + row + x0, o);
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t bx0 = tx * C::BPT + (cb + i) * C::BPC;
+                    if (bx0 >= a.g.nbx) continue;  // uniform
+                    const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                    const bool gvalid = bx < a.g.nbx;
+                    const uint32_t x0 = bx0 * B + (uint32_t)lane * V;
+                    DecState<DIM, B, V> st;
+                    st.init(a, bx, gvalid);
+                    dec_row<DIM, B, V>(a, st, c[i], 0, 0, x0, x0 < nx, gmask, lane, corrupt);
+                    if (leader && gvalid && st.rank != st.oe - st.os) corrupt = true;
                 }
             }
-            if (leader && gvalid && rank != oe - os) corrupt = true;
+        } else {
+            for (int ch = 0; ch < C::XCH; ++ch) {
+                const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
+                if (bx0 >= a.g.nbx) break;
+                const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                const bool gvalid = bx < a.g.nbx;
+                const uint32_t x0 = bx0 * B + (uint32_t)lane * V;
+                const bool xin = x0 < nx;
+                const uint32_t xl = min(x0, nx - V);
+                const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
+                DecState<DIM, B, V> st;
+                st.init(a, blk, gvalid);
+                // batches of NBR rows; the next batch is loaded while the
+                // current one is decoded
+                constexpr int YB = C::BY / C::NBR;  // batches per plane
+                auto load_batch = [&](int zl, int yb, uint32_t (&buf)[C::NBR][V]) {
+                    const uint32_t z = bz * B + zl;
+#pragma unroll
+                    for (int i = 0; i < C::NBR; ++i) {
+                        const uint32_t y = min(by * B + yb + i, ny - 1);  // clamped row
+                        load_codes<V>(a.codes + ((uint64_t)z * ny + y) * nx + xl, buf[i]);
+                    }
+                    // keep the loads here: the scheduler would otherwise sink
+                    // them to their first use and serialise memory and compute
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                auto decode_batch = [&](int zl, int yb, uint32_t (&buf)[C::NBR][V]) {
+                    dec_batch<DIM, B, V, C::NBR>(a, st, buf, yb, bz * B + zl, by * B + yb, x0, xin, gmask, lane,
+                                                 corrupt);
+                };
+                uint32_t bufA[C::NBR][V], bufB[C::NBR][V];
+                if constexpr (DIM == 3 && YB == 2) {
+                    const int nzl = (int)min((uint32_t)B, nz - bz * B);
+                    load_batch(0, 0, bufA);
+                    for (int zl = 0; zl < nzl; ++zl) {
+                        load_batch(zl, C::NBR, bufB);
+                        decode_batch(zl, 0, bufA);
+                        if (zl + 1 < nzl) load_batch(zl + 1, 0, bufA);
+                        decode_batch(zl, C::NBR, bufB);
+                    }
+                } else {
+                    const int nbt = DIM == 3 ? (int)min((uint32_t)B, nz - bz * B)
+                                             : (int)((min((uint32_t)B, ny - by * B) + C::NBR - 1) / C::NBR);
+                    load_batch(0, 0, bufA);
+                    for (int b = 0; b < nbt; b += 2) {
+                        if (b + 1 < nbt) load_batch((b + 1) / YB, ((b + 1) % YB) * C::NBR, bufB);
+                        decode_batch(b / YB, (b % YB) * C::NBR, bufA);
+                        if (b + 1 < nbt) {
+                            if (b + 2 < nbt) load_batch((b + 2) / YB, ((b + 2) % YB) * C::NBR, bufA);
+                            decode_batch((b + 1) / YB, ((b + 1) % YB) * C::NBR, bufB);
+                        }
+                    }
+                }
+                if (leader && gvalid && st.rank != st.oe - st.os) corrupt = true;
+            }
         }
     } else {
+        const uint32_t R = (uint32_t)a.R;
         for (int bi = 0; bi < C::BPT; ++bi) {
             const uint32_t bx = tx * C::BPT + bi;
             if (bx >= a.g.nbx) break;
@@ -161,63 +299,42 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
             }
             const uint32_t peff = block_peff<DIM>(a, bx);
             uint32_t rank = 0, carry = 0;
-            for (int ch = 0; ch < C::NCH; ++ch) {
-                const uint32_t xc = bx * B + ch * C::CX;
-                if (xc >= nx) break;
-                const uint32_t x0 = xc + (uint32_t)lane * V;
-                const bool xin = x0 < nx;
-                uint32_t c[V];
-                if (xin) {
-                    load_codes<V>(a.codes + x0, c);
-                } else {
+            for (int cb = 0; cb < C::NCH; cb += C::NBR) {
+                if (bx * B + cb * C::CX >= nx) break;
+                uint32_t c[C::NBR][V];
 #pragma unroll
-                    for (int j = 0; j < V; ++j) c[j] = R;
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t x0 = bx * B + (cb + i) * C::CX + (uint32_t)lane * V;
+                    load_codes<V>(a.codes + min(x0, nx - V), c[i]);
                 }
-                uint32_t d[V];
-                uint64_t m[V];
-                uint64_t any = 0;
 #pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    d[j] = c[j] - R;
-                    m[j] = ballot(c[j] == 0u);
-                    any |= m[j];
-                }
-                if (any) {
-                    uint32_t below = 0, tot = 0, own = 0;
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t xc = bx * B + (cb + i) * C::CX;
+                    if (xc >= nx) continue;  // uniform
+                    const uint32_t x0 = xc + (uint32_t)lane * V;
+                    const bool xin = x0 < nx;
+                    uint32_t cc[V], d[V];
 #pragma unroll
                     for (int j = 0; j < V; ++j) {
-                        below += mbcnt(m[j]);
-                        tot += popc(m[j]);
+                        cc[j] = xin ? c[i][j] : R;
+                        d[j] = cc[j] - R;
                     }
+                    fetch_outliers<V>(a, cc, d, rank, os, oe, ~0ull, x0, corrupt);
+                    uint32_t s[V];
+                    s[0] = d[0];
+#pragma unroll
+                    for (int j = 1; j < V; ++j) s[j] = s[j - 1] + d[j];
+                    const uint32_t incl = seg_scan_incl<64>(s[V - 1], lane);
+                    const uint32_t excl = incl - s[V - 1] + carry;
+                    carry += readlane(incl, 63);
+                    float o[V];
 #pragma unroll
                     for (int j = 0; j < V; ++j) {
-                        if (c[j] == 0u) {
-                            const uint32_t k = os + rank + below + own;
-                            ++own;
-                            if (k < oe && a.out_idx[k] == x0 + j) {
-                                d[j] = (uint32_t)a.out_val[k];
-                            } else {
-                                corrupt = true;
-                                d[j] = 0;
-                            }
-                        }
+                        const int32_t q = (int32_t)(s[j] + excl + peff);
+                        o[j] = (float)((double)q * a.twoeb);
                     }
-                    rank += tot;
+                    if (xin) store_f<V>(a.x_hat + x0, o);
                 }
-                uint32_t s[V];
-                s[0] = d[0];
-#pragma unroll
-                for (int j = 1; j < V; ++j) s[j] = s[j - 1] + d[j];
-                const uint32_t incl = seg_scan_incl<64>(s[V - 1], lane);
-                const uint32_t excl = incl - s[V - 1] + carry;
-                carry += readlane(incl, 63);
-                float o[V];
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const int32_t q = (int32_t)(s[j] + excl + peff);
-                    o[j] = (float)((double)q * twoeb);
-                }
-                if (xin) store_f<V>(a.x_hat + x0, o);
             }
             if (lane == 0 && rank != oe - os) corrupt = true;
         }

@@ -22,12 +22,13 @@ constexpr int kWaves = 4;                 // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
 constexpr int kStageCap = 256;            // LDS outlier staging entries per wave
 constexpr uint32_t kOriginFlag = 0x80000000u;
-constexpr int kTileTarget = 4096;         // minimum cells per tile
+constexpr int kTileTarget = 1024;         // minimum cells per tile (1-D, 2-D)
 
 constexpr int ST_OK = 0, ST_EINVAL = -1, ST_ERANGE = -2, ST_ECAPACITY = -3, ST_ECORRUPT = -6;
 constexpr int PAD_ZERO = 0, PAD_BLOCK = 1, PAD_EDGE = 2, PAD_GLOBAL = 3;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 template <int DIM, int B, int V>
 struct Cfg {
@@ -40,6 +41,12 @@ struct Cfg {
     static constexpr int BZ = DIM == 3 ? B : 1;
     static constexpr int XCH = WIDE ? 1 : cmax(1, kTileTarget / (CX * BY * BZ));
     static constexpr int BPT = WIDE ? cmax(1, kTileTarget / B) : XCH * BPC;  // blocks per tile
+    // rows whose loads are issued together before any is used (a batch): in
+    // 3-D a whole block plane or half of it (at most 32 registers of cells
+    // per lane), up to 8 rows in 2-D, up to 8 wave steps in 1-D
+    static constexpr int NBR = WIDE ? cmin(NCH, 8)
+                                    : (DIM == 3 ? cmin(BY, 32 / V) : (DIM == 2 ? cmin(BY, 8) : cmin(XCH, 8)));
+    static_assert(DIM != 3 || BY == NBR || BY == 2 * NBR, "3-D batches cover a plane or half of it");
     static_assert(V == 1 || V == 2 || V == 4, "V");
     static_assert(V <= B, "V <= B");
     static_assert(!WIDE || DIM == 1, "only 1-D blocks may be wider than a wave step");
@@ -62,13 +69,9 @@ struct Scalars {
     double eb;             // absolute error bound
     double twoeb;          // 2 eb
     double r;              // fp64 reciprocal of 2 eb (first estimate only)
-    double rel;            // relative factor (REL mode)
     unsigned long long sumq;   // int64 sum of q, two's complement (GLOBAL pad)
     unsigned int stage_count;  // outliers staged so far
-    unsigned int kmin, kmax;   // order-preserving keys of min(x), max(x)
-    unsigned int nonfinite;
     int gpad;                  // global pad value
-    int pad_;
 };
 
 struct EncArgs {
@@ -121,6 +124,11 @@ __device__ __forceinline__ uint32_t wave_shr1(uint32_t v) {
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// a value every lane holds identically, kept in a scalar register
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
 // Inclusive prefix sum of v over aligned segments of G lanes (G power of 2).
@@ -226,26 +234,37 @@ __device__ __forceinline__ double exact_round(float x, double k, double twoeb, d
     return k;
 }
 
+// `bad` accumulates (wave-wide) lanes whose q is out of range or x is not
+// finite. The fast path needs |x*r| <= 2^31 - 1.5 (then |q| <= 2^31 - 1
+// for sure) and x*r away from a half; every other lane - near a half, near or
+// past the range limit, non-finite - sends the wave through the exact path.
+constexpr double kFastMax = 2147483646.5;
+
 template <int V>
 __device__ __forceinline__ void prequant(const float (&x)[V], double r, double twoeb, double eb,
-                                         uint32_t (&q)[V], bool& bad) {
+                                         uint32_t (&q)[V], uint64_t& bad) {
     double k[V];
-    bool nh = false;
+    bool slow = false;
 #pragma unroll
     for (int j = 0; j < V; ++j) {
         const double v = (double)x[j] * r;
         k[j] = __builtin_rint(v);
-        nh |= __builtin_fabs(v - k[j]) > kNearHalf;
+        // false for NaN, so a non-finite x also takes the exact path
+        const bool fast = __builtin_fabs(v - k[j]) <= kNearHalf && __builtin_fabs(v) <= kFastMax;
+        slow = slow || !fast;
     }
-    if (__builtin_expect(ballot(nh) != 0, 0)) {
+    if (__builtin_expect(ballot(slow) != 0, 0)) {
+        bool out = false;
 #pragma unroll
-        for (int j = 0; j < V; ++j) k[j] = exact_round(x[j], k[j], twoeb, eb);
+        for (int j = 0; j < V; ++j) {
+            k[j] = exact_round(x[j], k[j], twoeb, eb);
+            out = out || !(__builtin_fabs(k[j]) <= kQMax);  // NaN and +-inf fail too
+            k[j] = __builtin_fabs(k[j]) <= kQMax ? k[j] : 0.0;
+        }
+        bad |= ballot(out);
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-        bad |= !(__builtin_fabs(k[j]) <= kQMax);
-        q[j] = (uint32_t)(int32_t)k[j];
-    }
+    for (int j = 0; j < V; ++j) q[j] = (uint32_t)(int32_t)k[j];
 }
 
 // ------------------------------------------------------------------ vector memory

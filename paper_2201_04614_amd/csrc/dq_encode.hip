@@ -1,7 +1,9 @@
 // dq_encode.hip - fused dual-quantisation encode kernel (gfx950).
 //
-// One pass over x per tile (see dq_device.hpp for the tiling):
-//   load V fp32 per lane (coalesced) -> q = round(x / 2eb)          (Section III-A)
+// One pass over x per tile (see dq_device.hpp for the tiling). Rows are
+// handled in batches whose loads are all in flight before the first use, the
+// next batch loading while the current one is computed:
+//   q = round(x / 2eb)                                                (Section III-A)
 //   -> zero-padded Lorenzo difference along x (DPP wave_shr:1), then y and z
 //      against the previous row / plane kept in registers
 //   -> code = delta + R or 0                                          (Section III-A)
@@ -11,6 +13,9 @@
 //      residual q_o - P_eff (the only residual that depends on the padding,
 //      because a face-constant halo cancels in every other Lorenzo
 //      difference), per-block outlier bookkeeping.
+// Inside a batch every phase is branch-free across rows; the two rare paths
+// (exact rounding near halves, outliers) are entered once per batch by the
+// whole wave, so the scheduler can interleave the independent rows.
 // A later scan over tiles and a scatter put the staged outliers in
 // block-major order.
 #include "dq_device.hpp"
@@ -18,24 +23,335 @@
 
 namespace dq {
 
+// Per-lane state of the blocks of one wave step.
+template <int DIM, int B, int V>
+struct EncState {
+    uint32_t rank;  // non-origin outliers found so far in this lane's block
+    long long s_all, s_fx, s_fy, s_fz;
+    uint32_t qo;
+    uint32_t dcode[V];
+    uint32_t pY[V];
+    uint32_t pZ[DIM == 3 ? B : 1][V];
+
+    __device__ __forceinline__ void init() {
+        rank = 0;
+        s_all = s_fx = s_fy = s_fz = 0;
+        qo = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            dcode[j] = 0;
+            pY[j] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < (DIM == 3 ? B : 1); ++k)
+#pragma unroll
+            for (int j = 0; j < V; ++j) pZ[k][j] = 0;
+    }
+};
+
+struct WaveCtx {
+    uint4* sbuf;
+    uint32_t scount;  // LDS staged entries (wave-uniform)
+    int lane;
+};
+
+__device__ __forceinline__ void stage_push(const EncArgs& a, WaveCtx& w, uint32_t tot) {
+    if (w.scount + tot > (uint32_t)kStageCap) {
+        flush_stage(w.sbuf, w.scount, a.stage, a.stage_cap, &a.sc->stage_count, w.lane);
+        w.scount = 0;
+    }
+}
+
+__device__ __forceinline__ bool is_inlier(uint32_t u, uint32_t R) { return u - 1u < 2u * R - 1u; }
+
+// Stage the outliers of one row (u = delta + R per cell). Called by the whole
+// wave; `origin` marks a lane whose first cell is its block's origin (that
+// one is classified at the end of the block).
+template <int V>
+__device__ __forceinline__ void stage_row_outliers(const EncArgs& a, uint32_t& rank, WaveCtx& w,
+                                                   const uint32_t (&u)[V], bool xin, bool origin,
+                                                   uint64_t row, uint32_t x0, uint64_t gmask, uint32_t blk) {
+    const uint32_t R = (uint32_t)a.R;
+    bool out[V];
+    uint64_t m[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        out[j] = xin && !is_inlier(u[j], R) && !(j == 0 && origin);
+        m[j] = ballot(out[j]);
+    }
+    uint32_t tot = 0, below = 0, gtot = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        tot += popc(m[j]);
+        below += mbcnt(m[j] & gmask);
+        gtot += popc(m[j] & gmask);
+    }
+    if (tot == 0) return;
+    stage_push(a, w, tot);
+    uint32_t slot = w.scount, own = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        if (out[j]) {
+            w.sbuf[slot + mbcnt(m[j])] = make_uint4((uint32_t)(row + x0 + j), u[j] - R, blk, rank + below + own);
+            ++own;
+        }
+        slot += popc(m[j]);
+    }
+    w.scount = uniform(w.scount + tot);
+    rank += gtot;
+}
+
+// Pre-quantisation of a batch of rows; the exact path runs once for the
+// batch when any lane needs it (see prequant).
+template <int V, int NR>
+__device__ __forceinline__ void prequant_rows(const float (&xv)[NR][V], double r, double twoeb, double eb,
+                                              uint32_t (&q)[NR][V], uint64_t& bad) {
+    bool slow = false;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const double v = (double)xv[i][j] * r;
+            const double k = __builtin_rint(v);
+            slow = slow || !(__builtin_fabs(v - k) <= kNearHalf && __builtin_fabs(v) <= kFastMax);
+            q[i][j] = (uint32_t)(int32_t)k;
+        }
+    }
+    if (__builtin_expect(ballot(slow) != 0, 0)) {
+        bool out = false;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                double k = __builtin_rint((double)xv[i][j] * r);
+                k = exact_round(xv[i][j], k, twoeb, eb);
+                const bool ok = __builtin_fabs(k) <= kQMax;  // NaN and +-inf fail too
+                out = out || !ok;
+                q[i][j] = (uint32_t)(int32_t)(ok ? k : 0.0);
+            }
+        }
+        bad |= ballot(out);
+    }
+}
+
+// One grid row of a 1-D step (a row of blocks): residuals, codes, statistics,
+// outliers.
+template <int DIM, int B, int V>
+__device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
+                                        const float (&xv)[V], uint64_t row, uint32_t x0, bool xin, bool leader,
+                                        uint64_t gmask, uint32_t blk, double r, double twoeb, double eb,
+                                        uint64_t& bad) {
+    const uint32_t R = (uint32_t)a.R;
+    uint32_t q[1][V];
+    const float(&x1)[1][V] = reinterpret_cast<const float(&)[1][V]>(xv);
+    prequant_rows<V, 1>(x1, r, twoeb, eb, q, bad);
+    const uint32_t left = wave_shr1(q[0][V - 1]);
+    uint32_t u[V];
+    u[0] = q[0][0] - (leader ? 0u : left) + R;
+#pragma unroll
+    for (int j = 1; j < V; ++j) u[j] = q[0][j] - q[0][j - 1] + R;
+    uint32_t code[V];
+    bool anyout = false;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        code[j] = is_inlier(u[j], R) ? u[j] : 0u;
+        anyout = anyout || (!is_inlier(u[j], R) && !(j == 0 && leader));
+    }
+    if (a.pad_mode == PAD_BLOCK) {
+        long long rs = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) rs += (int32_t)q[0][j];
+        st.s_all += xin ? rs : 0ll;
+    }
+    if (leader) {
+        st.qo = q[0][0];
+#pragma unroll
+        for (int j = 0; j < V; ++j) st.dcode[j] = code[j];
+    }
+    if (xin) store_codes<V>(a.codes + row + x0, code);  // the origin's code is rewritten at block end
+    if (ballot(xin && anyout)) stage_row_outliers<V>(a, st.rank, w, u, xin, leader, row, x0, gmask, blk);
+}
+
+// A batch of NR consecutive rows (local rows yb .. yb+NR-1 of local plane zl)
+// of a 2-D/3-D step.
+template <int DIM, int B, int V, int NR>
+__device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
+                                          const float (&xv)[NR][V], int zl, int yb, uint32_t z, uint32_t y0,
+                                          uint32_t x0, bool xin, bool leader, uint64_t gmask, uint32_t blk,
+                                          double r, double twoeb, double eb, uint64_t& bad) {
+    const uint32_t R = (uint32_t)a.R;
+    const uint32_t ny = a.g.ny, nx = a.g.nx;
+    // phase 1: pre-quantisation of every row
+    uint32_t q[NR][V];
+    prequant_rows<V, NR>(xv, r, twoeb, eb, q, bad);
+    // phase 2: Lorenzo residuals, u = delta + R (rows past the field edge
+    // only touch carries no valid row reads)
+    uint32_t u[NR][V];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int yl = yb + i;
+        const uint32_t left = wave_shr1(q[i][V - 1]);
+        uint32_t d[V];
+        d[0] = q[i][0] - (leader ? 0u : left);
+#pragma unroll
+        for (int j = 1; j < V; ++j) d[j] = q[i][j] - q[i][j - 1];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const uint32_t cur = d[j];
+            d[j] = (yl == 0) ? cur : cur - st.pY[j];
+            st.pY[j] = cur;
+        }
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const uint32_t cur = d[j];
+                d[j] = cur - st.pZ[yl][j];  // zero on the block's first plane
+                st.pZ[yl][j] = cur;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) u[i][j] = d[j] + R;
+    }
+    const bool orow0 = (zl == 0) && (yb == 0);  // this batch starts with the block's first row
+    // phase 3: codes (the origin's code is rewritten at the end of the block)
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        uint32_t code[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) code[j] = is_inlier(u[i][j], R) ? u[i][j] : 0u;
+        if (i == 0 && orow0 && leader) {
+            st.qo = q[0][0];
+#pragma unroll
+            for (int j = 0; j < V; ++j) st.dcode[j] = code[j];
+        }
+        if (xin && y0 + i < ny) store_codes<V>(a.codes + ((uint64_t)z * ny + y0 + i) * nx + x0, code);
+    }
+    // padding statistics (Section IV-A: mean of the data)
+    if (a.pad_mode == PAD_BLOCK || a.pad_mode == PAD_EDGE) {
+        const bool pb = a.pad_mode == PAD_BLOCK, pe = !pb;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const bool valid = xin && (y0 + i < ny);
+            long long rs = 0;
+#pragma unroll
+            for (int j = 0; j < V; ++j) rs += (int32_t)q[i][j];
+            rs = valid ? rs : 0ll;
+            st.s_all += pb ? rs : 0ll;
+            st.s_fx += (pe && valid && leader) ? (long long)(int32_t)q[i][0] : 0ll;
+            st.s_fy += (pe && yb + i == 0) ? rs : 0ll;
+            if constexpr (DIM == 3) st.s_fz += (pe && zl == 0) ? rs : 0ll;
+        }
+    }
+    // phase 4: outliers, rare
+    bool anyout = false;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            anyout = anyout || ((y0 + i < ny) && !is_inlier(u[i][j], R) && !(i == 0 && j == 0 && orow0 && leader));
+    }
+    if (ballot(xin && anyout)) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (y0 + i >= ny) continue;  // uniform
+            stage_row_outliers<V>(a, st.rank, w, u[i], xin, i == 0 && orow0 && leader,
+                                  ((uint64_t)z * ny + y0 + i) * nx, x0, gmask, blk);
+        }
+    }
+}
+
+// End of the blocks of one wave step: padding values, origin codes and the
+// per-block outlier bookkeeping. Returns the step's outlier count.
+template <int DIM, int B, int V>
+__device__ __forceinline__ uint32_t enc_block_end(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
+                                                  uint32_t bx, uint32_t by, uint32_t bz, uint32_t blk,
+                                                  uint32_t x0, bool gvalid, bool leader, uint32_t gpad,
+                                                  uint32_t tile_total) {
+    using C = Cfg<DIM, B, V>;
+    const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const uint32_t R = (uint32_t)a.R;
+    const int pad = a.pad_mode;
+    uint32_t peff = 0;
+    if (pad == PAD_GLOBAL) {
+        peff = gpad;
+    } else if (pad != PAD_ZERO) {
+        const long long ex = (long long)min((uint32_t)B, nx - min(nx, bx * B));
+        const long long ey = DIM >= 2 ? (long long)min((uint32_t)B, ny - by * B) : 1;
+        const long long ez = DIM == 3 ? (long long)min((uint32_t)B, nz - bz * B) : 1;
+        if (pad == PAD_BLOCK) {
+            const long long S = group_sum64<C::GPB>(st.s_all);
+            const int32_t P = round_mean(S, gvalid ? ex * ey * ez : 1);
+            peff = (uint32_t)P;
+            if (leader && gvalid) a.pads[blk] = P;
+        } else {
+            const long long Sx = group_sum64<C::GPB>(st.s_fx);
+            int32_t e[3] = {0, 0, 0};
+            if constexpr (DIM == 1) {
+                e[0] = (int32_t)st.qo;  // the x face of a 1-D block is its first cell
+            } else if constexpr (DIM == 2) {
+                const long long Sy = group_sum64<C::GPB>(st.s_fy);
+                e[0] = round_mean(Sy, gvalid ? ex : 1);  // axis 0 (y): first row
+                e[1] = round_mean(Sx, ey);               // axis 1 (x): first column
+            } else {
+                const long long Sy = group_sum64<C::GPB>(st.s_fy);
+                const long long Sz = group_sum64<C::GPB>(st.s_fz);
+                e[0] = round_mean(Sz, gvalid ? ex * ey : 1);  // axis 0 (z): first plane
+                e[1] = round_mean(Sy, gvalid ? ex * ez : 1);  // axis 1 (y)
+                e[2] = round_mean(Sx, ey * ez);               // axis 2 (x)
+            }
+            peff = edge_effective<DIM>(e);
+            if (leader && gvalid) {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) a.pads[(uint64_t)blk * DIM + k] = e[k];
+            }
+        }
+    }
+    bool oout = false;
+    uint32_t od = 0;
+    const uint64_t orow_base = ((uint64_t)(bz * B) * ny + by * B) * nx;
+    if (leader && gvalid) {
+        od = st.qo - peff;
+        const uint32_t u = od + R;
+        const bool inl = is_inlier(u, R);
+        st.dcode[0] = inl ? u : 0u;
+        oout = !inl;
+        store_codes<V>(a.codes + orow_base + x0, st.dcode);
+    }
+    const uint64_t mo = ballot(oout);
+    if (mo) {
+        const uint32_t n = popc(mo);
+        stage_push(a, w, n);
+        if (oout) w.sbuf[w.scount + mbcnt(mo)] = make_uint4((uint32_t)(orow_base + x0), od, blk, kOriginFlag);
+        w.scount = uniform(w.scount + n);
+    }
+    // per-block outlier counts -> exclusive prefix inside the tile
+    const uint32_t cnt = (leader && gvalid) ? st.rank + (oout ? 1u : 0u) : 0u;
+    uint32_t excl = 0, step_total = 0;
+    if (ballot(cnt != 0)) {
+        const uint32_t incl = wave_scan_incl(cnt, w.lane);
+        excl = incl - cnt;
+        step_total = readlane(incl, 63);
+    }
+    if (leader && gvalid) a.block_info[blk] = (tile_total + excl) | (oout ? kOriginFlag : 0u);
+    return step_total;
+}
+
 template <int DIM, int B, int V>
 __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
     using C = Cfg<DIM, B, V>;
     __shared__ uint4 sbuf_all[kWaves][kStageCap];
-    const int wave = threadIdx.x >> 6;
+    const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
-    uint4* sbuf = sbuf_all[wave];
     const uint32_t t = blockIdx.x * kWaves + wave;
     if (t >= a.g.n_tiles) return;
     if (__builtin_nontemporal_load(a.status) != ST_OK) {
         if (lane == 0) a.tile_count[t] = 0;
         return;
     }
+    WaveCtx w{sbuf_all[wave], 0u, lane};
     const double r = a.sc->r, twoeb = a.sc->twoeb, eb = a.sc->eb;
-    const uint32_t R = (uint32_t)a.R;
-    const int pad = a.pad_mode;
     uint32_t gpad = 0;
-    if (pad == PAD_GLOBAL) {
+    if (a.pad_mode == PAD_GLOBAL) {
         gpad = (uint32_t)round_mean((long long)a.sc->sumq, (long long)a.g.N);
         if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
     }
@@ -45,310 +361,169 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
     const uint32_t bz = rr / a.g.nby;
     const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
 
-    uint32_t scount = 0;      // LDS staged entries (wave-uniform)
     uint32_t tile_total = 0;  // outliers in this tile so far (wave-uniform)
-    bool bad = false;         // |q| out of range or x not finite
+    uint64_t bad = 0;         // lanes with |q| out of range or x not finite
 
     if constexpr (!C::WIDE) {
         const int gl = lane & (C::GPB - 1);
         const bool leader = gl == 0;
         const uint64_t gmask = (C::GPB == 64) ? ~0ull
                                               : (((1ull << C::GPB) - 1) << (lane & ~(C::GPB - 1)));
-        for (int ch = 0; ch < C::XCH; ++ch) {
-            const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
-            if (bx0 >= a.g.nbx) break;
-            const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
-            const bool gvalid = bx < a.g.nbx;
-            const uint32_t x0 = bx0 * B + (uint32_t)lane * V;
-            const bool xin = x0 < nx;
-            const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
-
-            uint32_t rank = 0;  // non-origin outliers found so far in this block
-            long long s_all = 0, s_fx = 0, s_fy = 0, s_fz = 0;
-            uint32_t qo = 0;
-            uint32_t dcode[V];
-            uint32_t pY[V];
-            uint32_t pZ[C::BY][V];
+        if constexpr (DIM == 1) {
+            // one row per step: batch NBR steps' loads
+            for (int cb = 0; cb < C::XCH; cb += C::NBR) {
+                if (tx * C::BPT + cb * C::BPC >= a.g.nbx) break;
+                float xv[C::NBR][V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) { dcode[j] = 0; pY[j] = 0; }
-
-            for (int zl = 0; zl < C::BZ; ++zl) {
-                const uint32_t z = bz * B + zl;
-                if (z >= nz) break;
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t x0 = (tx * C::BPT + (cb + i) * C::BPC) * B + (uint32_t)lane * V;
+                    load_f<V>(a.x + min(x0, nx - V), xv[i]);  // clamped: always in bounds
+                }
 #pragma unroll
-                for (int yl = 0; yl < C::BY; ++yl) {
-                    const uint32_t y = by * B + yl;
-                    if (y >= ny) continue;  // uniform: rows past the field edge
-                    const uint64_t row = ((uint64_t)z * ny + y) * nx;
-                    float xv[V];
-                    if (xin) {
-                        load_f<V>(a.x + row + x0, xv);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < V; ++j) xv[j] = 0.0f;
-                    }
-                    uint32_t q[V];
-                    prequant<V>(xv, r, twoeb, eb, q, bad);
-                    // Lorenzo residual with zero padding, separably: x, then y, then z
-                    const uint32_t left = wave_shr1(q[V - 1]);
-                    uint32_t d[V];
-                    d[0] = q[0] - (leader ? 0u : left);
-#pragma unroll
-                    for (int j = 1; j < V; ++j) d[j] = q[j] - q[j - 1];
-                    if constexpr (DIM >= 2) {
-#pragma unroll
-                        for (int j = 0; j < V; ++j) {
-                            const uint32_t cur = d[j];
-                            d[j] = (yl == 0) ? cur : cur - pY[j];
-                            pY[j] = cur;
-                        }
-                    }
-                    if constexpr (DIM == 3) {
-#pragma unroll
-                        for (int j = 0; j < V; ++j) {
-                            const uint32_t cur = d[j];
-                            d[j] = (zl == 0) ? cur : cur - pZ[yl][j];
-                            pZ[yl][j] = cur;
-                        }
-                    }
-                    // post-quantisation
-                    const bool orow = (zl == 0) && (yl == 0);
-                    uint32_t code[V];
-                    bool out[V];
-#pragma unroll
-                    for (int j = 0; j < V; ++j) {
-                        const uint32_t u = d[j] + (R - 1u);
-                        const bool inl = u < 2u * R - 1u;
-                        code[j] = inl ? u + 1u : 0u;
-                        out[j] = xin && !inl;
-                    }
-                    if (orow && leader) out[0] = false;  // classified at the end of the block
-                    // padding statistics (Section IV-A: mean of the data)
-                    if (pad == PAD_BLOCK) {
-                        if (xin) {
-#pragma unroll
-                            for (int j = 0; j < V; ++j) s_all += (int32_t)q[j];
-                        }
-                    } else if (pad == PAD_EDGE) {
-                        if (xin) {
-                            if (leader) s_fx += (int32_t)q[0];
-                            if (DIM >= 2 && yl == 0) {
-#pragma unroll
-                                for (int j = 0; j < V; ++j) s_fy += (int32_t)q[j];
-                            }
-                            if (DIM == 3 && zl == 0) {
-#pragma unroll
-                                for (int j = 0; j < V; ++j) s_fz += (int32_t)q[j];
-                            }
-                        }
-                    }
-                    if (orow && leader) {
-                        qo = q[0];
-#pragma unroll
-                        for (int j = 0; j < V; ++j) dcode[j] = code[j];
-                    } else if (xin) {
-                        store_codes<V>(a.codes + row + x0, code);
-                    }
-                    // outliers: rare path
-                    uint64_t m[V];
-                    uint64_t any = 0;
-#pragma unroll
-                    for (int j = 0; j < V; ++j) {
-                        m[j] = ballot(out[j]);
-                        any |= m[j];
-                    }
-                    if (any) {
-                        uint32_t tot = 0, below = 0, gtot = 0;
-#pragma unroll
-                        for (int j = 0; j < V; ++j) {
-                            tot += popc(m[j]);
-                            below += mbcnt(m[j] & gmask);
-                            gtot += popc(m[j] & gmask);
-                        }
-                        if (scount + tot > (uint32_t)kStageCap) {
-                            flush_stage(sbuf, scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
-                            scount = 0;
-                        }
-                        uint32_t slot = scount, own = 0;
-#pragma unroll
-                        for (int j = 0; j < V; ++j) {
-                            if (out[j]) {
-                                sbuf[slot + mbcnt(m[j])] =
-                                    make_uint4((uint32_t)(row + x0 + j), d[j], blk, rank + below + own);
-                                ++own;
-                            }
-                            slot += popc(m[j]);
-                        }
-                        scount += tot;
-                        rank += gtot;
-                    }
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t bx0 = tx * C::BPT + (cb + i) * C::BPC;
+                    if (bx0 >= a.g.nbx) continue;  // uniform
+                    const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                    const bool gvalid = bx < a.g.nbx;
+                    const uint32_t x0 = bx0 * B + (uint32_t)lane * V;
+                    const bool xin = x0 < nx;
+                    EncState<DIM, B, V> st;
+                    st.init();
+                    enc_row<DIM, B, V>(a, st, w, xv[i], 0, x0, xin, leader, gmask, bx, r, twoeb, eb, bad);
+                    tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, 0, 0, bx, x0, gvalid, leader,
+                                                           gpad, tile_total);
                 }
             }
-
-            // ---- end of the blocks of this step: padding and origins
-            uint32_t peff = 0;
-            if (pad == PAD_GLOBAL) {
-                peff = gpad;
-            } else if (pad != PAD_ZERO) {
-                const long long ex = (long long)min((uint32_t)B, nx - min(nx, bx * B));
-                const long long ey = DIM >= 2 ? (long long)min((uint32_t)B, ny - by * B) : 1;
-                const long long ez = DIM == 3 ? (long long)min((uint32_t)B, nz - bz * B) : 1;
-                if (pad == PAD_BLOCK) {
-                    const long long S = group_sum64<C::GPB>(s_all);
-                    const int32_t P = round_mean(S, gvalid ? ex * ey * ez : 1);
-                    peff = (uint32_t)P;
-                    if (leader && gvalid) a.pads[blk] = P;
+        } else {
+            for (int ch = 0; ch < C::XCH; ++ch) {
+                const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
+                if (bx0 >= a.g.nbx) break;
+                const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                const bool gvalid = bx < a.g.nbx;
+                const uint32_t x0 = bx0 * B + (uint32_t)lane * V;
+                const bool xin = x0 < nx;
+                const uint32_t xl = min(x0, nx - V);  // clamped load column
+                const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
+                EncState<DIM, B, V> st;
+                st.init();
+                // batches of NBR rows in local row-major order; the next batch
+                // is loaded while the current one is computed
+                constexpr int YB = C::BY / C::NBR;  // batches per plane
+                auto load_batch = [&](int zl, int yb, float (&buf)[C::NBR][V]) {
+                    const uint32_t z = bz * B + zl;
+#pragma unroll
+                    for (int i = 0; i < C::NBR; ++i) {
+                        const uint32_t y = min(by * B + yb + i, ny - 1);  // clamped row
+                        load_f<V>(a.x + ((uint64_t)z * ny + y) * nx + xl, buf[i]);
+                    }
+                    // keep the loads here: the scheduler would otherwise sink
+                    // them to their first use and serialise memory and compute
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                auto compute_batch = [&](int zl, int yb, float (&buf)[C::NBR][V]) {
+                    enc_batch<DIM, B, V, C::NBR>(a, st, w, buf, zl, yb, bz * B + zl, by * B + yb, x0, xin,
+                                                 leader, gmask, blk, r, twoeb, eb, bad);
+                };
+                float bufA[C::NBR][V], bufB[C::NBR][V];
+                if constexpr (DIM == 3 && YB == 2) {
+                    // two batches per plane: buffer A holds rows 0..NBR-1, B the rest
+                    const int nzl = (int)min((uint32_t)B, nz - bz * B);
+                    load_batch(0, 0, bufA);
+                    for (int zl = 0; zl < nzl; ++zl) {
+                        load_batch(zl, C::NBR, bufB);
+                        compute_batch(zl, 0, bufA);
+                        if (zl + 1 < nzl) load_batch(zl + 1, 0, bufA);
+                        compute_batch(zl, C::NBR, bufB);
+                    }
                 } else {
-                    const long long Sx = group_sum64<C::GPB>(s_fx);
-                    int32_t e[3] = {0, 0, 0};
-                    if constexpr (DIM == 1) {
-                        e[0] = (int32_t)qo;  // the x face of a 1-D block is its first cell
-                    } else if constexpr (DIM == 2) {
-                        const long long Sy = group_sum64<C::GPB>(s_fy);
-                        e[0] = round_mean(Sy, gvalid ? ex : 1);  // axis 0 (y): first row
-                        e[1] = round_mean(Sx, ey);               // axis 1 (x): first column
-                    } else {
-                        const long long Sy = group_sum64<C::GPB>(s_fy);
-                        const long long Sz = group_sum64<C::GPB>(s_fz);
-                        e[0] = round_mean(Sz, gvalid ? ex * ey : 1);  // axis 0 (z): first plane
-                        e[1] = round_mean(Sy, gvalid ? ex * ez : 1);  // axis 1 (y)
-                        e[2] = round_mean(Sx, ey * ez);               // axis 2 (x)
-                    }
-                    peff = edge_effective<DIM>(e);
-                    if (leader && gvalid) {
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) a.pads[(uint64_t)blk * DIM + k] = e[k];
+                    static_assert(DIM == 2 || YB == 1, "3-D batches cover a whole plane or half of it");
+                    // batch b covers plane b / YB, rows (b % YB) * NBR ...
+                    const int nbt = DIM == 3 ? (int)min((uint32_t)B, nz - bz * B)
+                                             : (int)((min((uint32_t)B, ny - by * B) + C::NBR - 1) / C::NBR);
+                    load_batch(0, 0, bufA);
+                    // both buffers in flight, issued in the order they are
+                    // consumed, so each wait covers only the batch it needs
+                    if (nbt > 1) load_batch(1 / YB, (1 % YB) * C::NBR, bufB);
+                    for (int b = 0; b < nbt; b += 2) {
+                        compute_batch(b / YB, (b % YB) * C::NBR, bufA);
+                        if (b + 2 < nbt) load_batch((b + 2) / YB, ((b + 2) % YB) * C::NBR, bufA);
+                        if (b + 1 < nbt) {
+                            compute_batch((b + 1) / YB, ((b + 1) % YB) * C::NBR, bufB);
+                            if (b + 3 < nbt) load_batch((b + 3) / YB, ((b + 3) % YB) * C::NBR, bufB);
+                        }
                     }
                 }
+                tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, by, bz, blk, x0, gvalid, leader, gpad,
+                                                       tile_total);
             }
-            bool oout = false;
-            uint32_t od = 0;
-            const uint64_t orow_base = ((uint64_t)(bz * B) * ny + by * B) * nx;
-            if (leader && gvalid) {
-                od = qo - peff;
-                const uint32_t u = od + (R - 1u);
-                const bool inl = u < 2u * R - 1u;
-                dcode[0] = inl ? u + 1u : 0u;
-                oout = !inl;
-                store_codes<V>(a.codes + orow_base + x0, dcode);
-            }
-            const uint64_t mo = ballot(oout);
-            if (mo) {
-                const uint32_t n = popc(mo);
-                if (scount + n > (uint32_t)kStageCap) {
-                    flush_stage(sbuf, scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
-                    scount = 0;
-                }
-                if (oout)
-                    sbuf[scount + mbcnt(mo)] = make_uint4((uint32_t)(orow_base + x0), od, blk, kOriginFlag);
-                scount += n;
-            }
-            // per-block outlier counts -> exclusive prefix inside the tile
-            const uint32_t cnt = (leader && gvalid) ? rank + (oout ? 1u : 0u) : 0u;
-            uint32_t excl = 0, step_total = 0;
-            if (ballot(cnt != 0)) {
-                const uint32_t incl = wave_scan_incl(cnt, lane);
-                excl = incl - cnt;
-                step_total = readlane(incl, 63);
-            }
-            if (leader && gvalid) a.block_info[blk] = (tile_total + excl) | (oout ? kOriginFlag : 0u);
-            tile_total += step_total;
         }
     } else {
         // 1-D blocks wider than one wave step: blocks one after another
-        const uint32_t nblk = a.g.nbx;
+        const uint32_t R = (uint32_t)a.R;
         for (int bi = 0; bi < C::BPT; ++bi) {
             const uint32_t bx = tx * C::BPT + bi;
-            if (bx >= nblk) break;
+            if (bx >= a.g.nbx) break;
             uint32_t rank = 0, carry = 0, qo = 0;
             long long s_all = 0;
             uint32_t dcode[V];
 #pragma unroll
             for (int j = 0; j < V; ++j) dcode[j] = 0;
-            for (int ch = 0; ch < C::NCH; ++ch) {
-                const uint32_t xc = bx * B + ch * C::CX;
-                if (xc >= nx) break;
-                const uint32_t x0 = xc + (uint32_t)lane * V;
-                const bool xin = x0 < nx;
-                float xv[V];
-                if (xin) {
-                    load_f<V>(a.x + x0, xv);
-                } else {
+            for (int cb = 0; cb < C::NCH; cb += C::NBR) {
+                if (bx * B + cb * C::CX >= nx) break;
+                float xv[C::NBR][V];
 #pragma unroll
-                    for (int j = 0; j < V; ++j) xv[j] = 0.0f;
+                for (int i = 0; i < C::NBR; ++i) {
+                    const uint32_t x0 = bx * B + (cb + i) * C::CX + (uint32_t)lane * V;
+                    load_f<V>(a.x + min(x0, nx - V), xv[i]);
                 }
-                uint32_t q[V];
-                prequant<V>(xv, r, twoeb, eb, q, bad);
-                uint32_t left = wave_shr1(q[V - 1]);
-                if (lane == 0) left = carry;  // 0 at the block start
-                carry = readlane(q[V - 1], 63);
-                uint32_t d[V];
-                d[0] = q[0] - left;
+                uint32_t q[C::NBR][V];
+                prequant_rows<V, C::NBR>(xv, r, twoeb, eb, q, bad);
 #pragma unroll
-                for (int j = 1; j < V; ++j) d[j] = q[j] - q[j - 1];
-                const bool origin_lane = (ch == 0) && (lane == 0);
-                uint32_t code[V];
-                bool out[V];
+                for (int i = 0; i < C::NBR; ++i) {
+                    const int ch = cb + i;
+                    const uint32_t xc = bx * B + ch * C::CX;
+                    if (xc >= nx) continue;  // uniform
+                    const uint32_t x0 = xc + (uint32_t)lane * V;
+                    const bool xin = x0 < nx;
+                    uint32_t left = wave_shr1(q[i][V - 1]);
+                    if (lane == 0) left = carry;  // 0 at the block start
+                    carry = readlane(q[i][V - 1], 63);
+                    uint32_t u[V];
+                    u[0] = q[i][0] - left + R;
 #pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const uint32_t u = d[j] + (R - 1u);
-                    const bool inl = u < 2u * R - 1u;
-                    code[j] = inl ? u + 1u : 0u;
-                    out[j] = xin && !inl;
-                }
-                if (origin_lane) out[0] = false;
-                if (pad == PAD_BLOCK && xin) {
-#pragma unroll
-                    for (int j = 0; j < V; ++j) s_all += (int32_t)q[j];
-                }
-                if (origin_lane) {
-                    qo = q[0];
-#pragma unroll
-                    for (int j = 0; j < V; ++j) dcode[j] = code[j];
-                } else if (xin) {
-                    store_codes<V>(a.codes + x0, code);
-                }
-                uint64_t m[V];
-                uint64_t any = 0;
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    m[j] = ballot(out[j]);
-                    any |= m[j];
-                }
-                if (any) {
-                    uint32_t tot = 0, below = 0;
+                    for (int j = 1; j < V; ++j) u[j] = q[i][j] - q[i][j - 1] + R;
+                    const bool origin_lane = (ch == 0) && (lane == 0);
+                    uint32_t code[V];
+                    bool anyout = false;
 #pragma unroll
                     for (int j = 0; j < V; ++j) {
-                        tot += popc(m[j]);
-                        below += mbcnt(m[j]);
+                        code[j] = is_inlier(u[j], R) ? u[j] : 0u;
+                        anyout = anyout || (!is_inlier(u[j], R) && !(j == 0 && origin_lane));
                     }
-                    if (scount + tot > (uint32_t)kStageCap) {
-                        flush_stage(sbuf, scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
-                        scount = 0;
-                    }
-                    uint32_t slot = scount, own = 0;
+                    if (a.pad_mode == PAD_BLOCK && xin) {
 #pragma unroll
-                    for (int j = 0; j < V; ++j) {
-                        if (out[j]) {
-                            sbuf[slot + mbcnt(m[j])] = make_uint4(x0 + j, d[j], bx, rank + below + own);
-                            ++own;
-                        }
-                        slot += popc(m[j]);
+                        for (int j = 0; j < V; ++j) s_all += (int32_t)q[i][j];
                     }
-                    scount += tot;
-                    rank += tot;
+                    if (origin_lane) {
+                        qo = q[i][0];
+#pragma unroll
+                        for (int j = 0; j < V; ++j) dcode[j] = code[j];
+                    }
+                    if (xin) store_codes<V>(a.codes + x0, code);  // origin rewritten at block end
+                    if (ballot(xin && anyout))
+                        stage_row_outliers<V>(a, rank, w, u, xin, origin_lane, 0, x0, ~0ull, bx);
                 }
             }
             uint32_t peff = 0;
-            if (pad == PAD_GLOBAL) {
+            if (a.pad_mode == PAD_GLOBAL) {
                 peff = gpad;
-            } else if (pad == PAD_BLOCK) {
+            } else if (a.pad_mode == PAD_BLOCK) {
                 const long long S = group_sum64<64>(s_all);
                 const long long ex = (long long)min((uint32_t)B, nx - bx * B);
                 const int32_t P = round_mean(S, ex);
                 peff = (uint32_t)P;
                 if (lane == 0) a.pads[bx] = P;
-            } else if (pad == PAD_EDGE) {
+            } else if (a.pad_mode == PAD_EDGE) {
                 peff = readlane(qo, 0);
                 if (lane == 0) a.pads[bx] = (int32_t)peff;
             }
@@ -356,19 +531,16 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
             uint32_t od = 0;
             if (lane == 0) {
                 od = qo - peff;
-                const uint32_t u = od + (R - 1u);
-                const bool inl = u < 2u * R - 1u;
-                dcode[0] = inl ? u + 1u : 0u;
+                const uint32_t u = od + R;
+                const bool inl = is_inlier(u, R);
+                dcode[0] = inl ? u : 0u;
                 oout = !inl;
                 store_codes<V>(a.codes + (uint64_t)bx * B, dcode);
             }
             if (ballot(oout)) {
-                if (scount + 1 > (uint32_t)kStageCap) {
-                    flush_stage(sbuf, scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
-                    scount = 0;
-                }
-                if (lane == 0) sbuf[scount] = make_uint4(bx * B, od, bx, kOriginFlag);
-                scount += 1;
+                stage_push(a, w, 1);
+                if (lane == 0) w.sbuf[w.scount] = make_uint4(bx * B, od, bx, kOriginFlag);
+                w.scount = uniform(w.scount + 1);
             }
             const uint32_t cnt = readlane(rank + (oout ? 1u : 0u), 0);
             if (lane == 0) a.block_info[bx] = tile_total | (oout ? kOriginFlag : 0u);
@@ -376,9 +548,9 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
         }
     }
 
-    if (scount) flush_stage(sbuf, scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
+    if (w.scount) flush_stage(w.sbuf, w.scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
     if (lane == 0) a.tile_count[t] = tile_total;
-    if (ballot(bad) && lane == 0) __hip_atomic_store(a.status, ST_ERANGE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bad && lane == 0) __hip_atomic_store(a.status, ST_ERANGE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 #define DQ_ENC_CASE(D, BB, VV)                                              \

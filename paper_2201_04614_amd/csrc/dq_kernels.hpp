@@ -40,10 +40,11 @@ struct AuxArgs {
     uint64_t N;
 };
 
-void launch_compress_init(Scalars* sc, int32_t* status, void* res, double eb, double rel, int eb_mode,
-                          hipStream_t stream);
-void launch_minmax(const AuxArgs& a, hipStream_t stream);
-void launch_resolve_rel(Scalars* sc, int32_t* status, void* res, hipStream_t stream);
+constexpr int kMinmaxParts = 1024;  // value-range partials (one per workgroup)
+
+void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream);
+int launch_minmax(const AuxArgs& a, uint4* parts, hipStream_t stream);
+void launch_resolve_rel(Scalars* sc, void* res, const uint4* parts, int nparts, double rel, hipStream_t stream);
 void launch_sumq(const AuxArgs& a, hipStream_t stream);
 void launch_scan_tiles(uint32_t* tile_count, uint32_t n_tiles, Scalars* sc, int32_t* status, void* res,
                        uint64_t out_cap, hipStream_t stream);

@@ -13,13 +13,13 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_compress(x, eb, eb_mode, block, pad, radius, out_cap=None, x_dev=None):
+def gpu_compress(x, eb, eb_mode, block, pad, radius, out_cap=None, x_dev=None, vec=0):
     """Compress on the GPU; returns host copies of everything."""
     import torch
     if x_dev is None:
         x_dev = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     codec = dq.Codec(x.shape, eb, eb_mode, block, pad, radius,
-                     out_cap=x.size if out_cap is None else out_cap)
+                     out_cap=x.size if out_cap is None else out_cap, vec=vec)
     codec.compress_async(x_dev)
     r = codec.result()
     n = int(r.n_out)
@@ -66,12 +66,12 @@ def assert_same_compress(g, c, ctx=""):
 
 
 def parity(ref, x, eb, eb_mode="abs", block=16, pad="zero", radius=512, nthreads=0,
-           check_decode=True, x_dev=None):
+           check_decode=True, x_dev=None, vec=0):
     """Full comparison of compress and decompress; returns the oracle result."""
     ctx = f"shape={x.shape} eb={eb} {eb_mode} B={block} pad={pad} R={radius}"
     p = ref.params(x.shape, eb, eb_mode, block, pad, radius)
     c = ref.compress(p, x, nthreads=nthreads)
-    g = gpu_compress(x, eb, eb_mode, block, pad, radius, x_dev=x_dev)
+    g = gpu_compress(x, eb, eb_mode, block, pad, radius, x_dev=x_dev, vec=vec)
     assert_same_compress(g, c, ctx)
     if c.status == 0 and check_decode:
         st, xr = ref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads, nthreads=nthreads)

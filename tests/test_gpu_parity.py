@@ -183,3 +183,18 @@ def test_determinism(ref):
     for k in ("codes", "out_idx", "out_val", "pads"):
         assert np.array_equal(a[k], b[k])
     assert a["n_out"] == b["n_out"] > 0
+
+
+@pytest.mark.parametrize("vec", [1, 2, 4])
+def test_vector_width_hint(ref, vec):
+    """Every load width the tuning hint can select gives the oracle's bytes."""
+    x = F.power_law_grf((40, 64, 96), seed=8) + np.float32(4.0)
+    for B in (4, 8, 16):
+        for pad in PADS:
+            G.parity(ref, x, 1e-4, "rel", B, pad, 512, vec=vec)
+    x2 = F.sinusoid_field((96, 200), seed=8)
+    for B in (8, 64):
+        G.parity(ref, x2, 1e-3 * F.field_range(x2), "abs", B, "edge_mean", 64, vec=vec)
+    x1 = F.uniform_field((30000,), seed=8)
+    for B in (16, 1024):
+        G.parity(ref, x1, 1e-3, "abs", B, "block_mean", 128, vec=vec)
