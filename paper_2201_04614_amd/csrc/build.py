@@ -17,7 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libdq.so")
-SOURCES = ["dq_api.hip", "dq_encode.hip", "dq_decode.hip", "dq_aux.hip"]
+# (source, object, extra flags): the encode and decode kernels are compiled
+# once per dimensionality so their instantiations build in parallel
+UNITS = [("dq_api.hip", "dq_api.o", []), ("dq_aux.hip", "dq_aux.o", [])] + [
+    (f"dq_{k}.hip", f"dq_{k}_{d}d.o", [f"-DDQ_DIM={d}"]) for k in ("encode", "decode") for d in (1, 2, 3)]
 ARCH = os.environ.get("DQ_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
@@ -25,8 +28,8 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
 
 
-def _compile(src, obj, verbose):
-    cmd = ["hipcc", "-c", *CFLAGS, "-o", obj, os.path.join(HERE, src)]
+def _compile(src, obj, extra, verbose):
+    cmd = ["hipcc", "-c", *CFLAGS, *extra, "-o", obj, os.path.join(HERE, src)]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -40,10 +43,10 @@ def _compile(src, obj, verbose):
 def build(verbose=False, jobs=None):
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    objs = [os.path.join(objdir, o) for _, o, _ in UNITS]
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(SOURCES, objs)))
+        list(ex.map(lambda u: _compile(u[0], os.path.join(objdir, u[1]), u[2], verbose), UNITS))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:

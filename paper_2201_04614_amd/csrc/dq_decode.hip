@@ -130,10 +130,12 @@ __device__ __forceinline__ void dec_row(const DecArgs& a, DecState<DIM, B, V>& s
 // A batch of NR consecutive rows (local rows yb .. yb+NR-1 of local plane zl)
 // of a 2-D/3-D step: the outlier lookup is entered once per batch by the
 // whole wave, the prefix sums and dequantisation are branch-free across rows.
-template <int DIM, int B, int V, int NR>
+// FULL: every row and lane lies inside the field; row i is written to
+// orow + i*nx + lane*V (orow is wave-uniform) with no per-lane condition.
+template <int DIM, int B, int V, int NR, bool FULL>
 __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[NR][V],
                                           int yb, uint32_t z, uint32_t y0, uint32_t x0, bool xin, uint64_t gmask,
-                                          int lane, bool& corrupt) {
+                                          int lane, bool& corrupt, float* orow = nullptr) {
     using C = Cfg<DIM, B, V>;
     const uint32_t R = (uint32_t)a.R;
     const uint32_t ny = a.g.ny, nx = a.g.nx;
@@ -143,18 +145,18 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
     for (int i = 0; i < NR; ++i) {
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const uint32_t cc = xin ? c[i][j] : R;  // lanes past the field edge decode zeros
+            const uint32_t cc = (FULL || xin) ? c[i][j] : R;  // lanes past the field edge decode zeros
             d[i][j] = cc - R;
-            anyzero = anyzero || (cc == 0u && y0 + i < ny);
+            anyzero = anyzero || (cc == 0u && (FULL || y0 + i < ny));
         }
     }
     if (ballot(anyzero)) {  // rare: rows in order, so ranks follow local row-major order
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            if (y0 + i >= ny) continue;  // uniform
+            if (!FULL && y0 + i >= ny) continue;  // uniform
             uint32_t cc[V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) cc[j] = xin ? c[i][j] : R;
+            for (int j = 0; j < V; ++j) cc[j] = (FULL || xin) ? c[i][j] : R;
             fetch_outliers<V>(a, cc, d[i], st.rank, st.os, st.oe, gmask, ((uint64_t)z * ny + y0 + i) * nx + x0,
                               corrupt);
         }
@@ -182,7 +184,10 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
             const int32_t q = (int32_t)(p + st.peff);
             o[j] = (float)((double)q * a.twoeb);
         }
-        if (xin && y0 + i < ny) store_f<V>(a.x_hat + ((uint64_t)z * ny + y0 + i) * nx + x0, o);
+        if constexpr (FULL)
+            store_f<V>(orow + (uint64_t)i * nx + (uint32_t)(lane * V), o);
+        else if (xin && y0 + i < ny)
+            store_f<V>(a.x_hat + ((uint64_t)z * ny + y0 + i) * nx + x0, o);
     }
 }
 
@@ -231,6 +236,45 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
                     if (leader && gvalid && st.rank != st.oe - st.os) corrupt = true;
                 }
             }
+        } else if (C::NBT * C::NBR <= kMaxUnrollRows && (tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny &&
+                   (bz + 1) * C::BZ <= nz) {
+            // Interior tile: the block row is one straight-line sequence of
+            // NBT batches with kPipeDepth batches of loads in flight ahead of
+            // the one being decoded; loads and stores are unconditional and
+            // addressed from wave-uniform row bases.
+            constexpr int NBT = C::NBT;
+            constexpr int D = cmin(NBT, kPipeDepth);
+            constexpr int YB = C::BY / C::NBR;  // batches per plane
+            const uint32_t voff = (uint32_t)lane * V;
+            for (int ch = 0; ch < C::XCH; ++ch) {
+                const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
+                const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                const uint32_t x0 = bx0 * B + voff;
+                const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
+                const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
+                const uint16_t* cb = a.codes + base;
+                float* ob = a.x_hat + base;
+                DecState<DIM, B, V> st;
+                st.init(a, blk, true);
+                uint32_t buf[D][C::NBR][V];
+                auto load = [&](auto bI, uint32_t (&bb)[C::NBR][V]) {
+                    constexpr int b = decltype(bI)::value;
+                    const uint16_t* p = cb + ((uint64_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
+#pragma unroll
+                    for (int i = 0; i < C::NBR; ++i) load_codes<V>(p + (uint64_t)i * nx + voff, bb[i]);
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
+                static_for<0, NBT>([&](auto bI) {
+                    constexpr int b = decltype(bI)::value;
+                    constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
+                    dec_batch<DIM, B, V, C::NBR, true>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb, x0,
+                                                       true, gmask, lane, corrupt,
+                                                       ob + ((uint64_t)zl * ny + yb) * nx);
+                    if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
+                });
+                if (leader && st.rank != st.oe - st.os) corrupt = true;
+            }
         } else {
             for (int ch = 0; ch < C::XCH; ++ch) {
                 const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
@@ -258,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
                     __builtin_amdgcn_sched_barrier(0);
                 };
                 auto decode_batch = [&](int zl, int yb, uint32_t (&buf)[C::NBR][V]) {
-                    dec_batch<DIM, B, V, C::NBR>(a, st, buf, yb, bz * B + zl, by * B + yb, x0, xin, gmask, lane,
+                    dec_batch<DIM, B, V, C::NBR, false>(a, st, buf, yb, bz * B + zl, by * B + yb, x0, xin, gmask, lane,
                                                  corrupt);
                 };
                 uint32_t bufA[C::NBR][V], bufB[C::NBR][V];
@@ -342,13 +386,26 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     if (ballot(corrupt) && lane == 0) mark_corrupt(a.status);
 }
 
-#define DQ_DEC_CASE(D, BB, VV)                                              \
-    if (dim == D && block == BB && v == VV) {                               \
-        hipLaunchKernelGGL((k_decode<D, BB, VV>), grid, dim3(kThreads), 0, stream, a); \
-        return true;                                                        \
-    }
+#ifndef DQ_DIM
+#error "dq_decode.hip is compiled once per DQ_DIM (1, 2, 3)"
+#endif
 
-bool launch_decode(int dim, int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
+// instantiated only for the configurations of this object's dimensionality
+template <int D, int BB, int VV>
+static bool try_launch_decode(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
+    if constexpr (D == DQ_DIM) {
+        if (block == BB && v == VV) {
+            hipLaunchKernelGGL((k_decode<D, BB, VV>), grid, dim3(kThreads), 0, stream, a);
+            return true;
+        }
+    }
+    return false;
+}
+
+#define DQ_DEC_CASE(D, BB, VV) \
+    if (try_launch_decode<D, BB, VV>(block, v, a, grid, stream)) return true;
+
+bool DQ_CAT(launch_decode_dim, DQ_DIM)(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
     DQ_CONFIGS(DQ_DEC_CASE)
     return false;
 }

@@ -30,6 +30,29 @@ constexpr int PAD_ZERO = 0, PAD_BLOCK = 1, PAD_EDGE = 2, PAD_GLOBAL = 3;
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
+// Batches of rows kept in flight ahead of the one being computed (interior
+// tiles; see k_encode / k_decode) and the most grid rows of a block row that
+// are unrolled into straight-line code.
+#ifndef DQ_PIPE_DEPTH
+#define DQ_PIPE_DEPTH 3
+#endif
+constexpr int kPipeDepth = DQ_PIPE_DEPTH;
+constexpr int kMaxUnrollRows = 64;
+
+template <int I>
+struct Idx {
+    static constexpr int value = I;
+};
+
+// f(Idx<I>{}) for I = FIRST .. LAST-1, expanded at compile time
+template <int FIRST, int LAST, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (FIRST < LAST) {
+        f(Idx<FIRST>{});
+        static_for<FIRST + 1, LAST>(f);
+    }
+}
+
 template <int DIM, int B, int V>
 struct Cfg {
     static constexpr int CX = 64 * V;                       // cells per wave step
@@ -47,6 +70,8 @@ struct Cfg {
     static constexpr int NBR = WIDE ? cmin(NCH, 8)
                                     : (DIM == 3 ? cmin(BY, 32 / V) : (DIM == 2 ? cmin(BY, 8) : cmin(XCH, 8)));
     static_assert(DIM != 3 || BY == NBR || BY == 2 * NBR, "3-D batches cover a plane or half of it");
+    // batches per block row of a complete block (2-D / 3-D)
+    static constexpr int NBT = DIM == 3 ? BZ * (BY / NBR) : (DIM == 2 ? BY / NBR : 1);
     static_assert(V == 1 || V == 2 || V == 4, "V");
     static_assert(V <= B, "V <= B");
     static_assert(!WIDE || DIM == 1, "only 1-D blocks may be wider than a wave step");

@@ -173,12 +173,15 @@ __device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& s
 }
 
 // A batch of NR consecutive rows (local rows yb .. yb+NR-1 of local plane zl)
-// of a 2-D/3-D step.
-template <int DIM, int B, int V, int NR>
+// of a 2-D/3-D step. FULL: every row and lane lies inside the field; the
+// codes of row i go to crow + i*nx + lane*V (crow is wave-uniform), with no
+// per-lane condition, so every store is issued on every path.
+template <int DIM, int B, int V, int NR, bool FULL>
 __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
                                           const float (&xv)[NR][V], int zl, int yb, uint32_t z, uint32_t y0,
                                           uint32_t x0, bool xin, bool leader, uint64_t gmask, uint32_t blk,
-                                          double r, double twoeb, double eb, uint64_t& bad) {
+                                          double r, double twoeb, double eb, uint64_t& bad,
+                                          uint16_t* crow = nullptr) {
     const uint32_t R = (uint32_t)a.R;
     const uint32_t ny = a.g.ny, nx = a.g.nx;
     // phase 1: pre-quantisation of every row
@@ -224,14 +227,17 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
 #pragma unroll
             for (int j = 0; j < V; ++j) st.dcode[j] = code[j];
         }
-        if (xin && y0 + i < ny) store_codes<V>(a.codes + ((uint64_t)z * ny + y0 + i) * nx + x0, code);
+        if constexpr (FULL)
+            store_codes<V>(crow + (uint64_t)i * nx + (uint32_t)(w.lane * V), code);
+        else if (xin && y0 + i < ny)
+            store_codes<V>(a.codes + ((uint64_t)z * ny + y0 + i) * nx + x0, code);
     }
     // padding statistics (Section IV-A: mean of the data)
     if (a.pad_mode == PAD_BLOCK || a.pad_mode == PAD_EDGE) {
         const bool pb = a.pad_mode == PAD_BLOCK, pe = !pb;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const bool valid = xin && (y0 + i < ny);
+            const bool valid = FULL || (xin && (y0 + i < ny));
             long long rs = 0;
 #pragma unroll
             for (int j = 0; j < V; ++j) rs += (int32_t)q[i][j];
@@ -248,13 +254,14 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
     for (int i = 0; i < NR; ++i) {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-            anyout = anyout || ((y0 + i < ny) && !is_inlier(u[i][j], R) && !(i == 0 && j == 0 && orow0 && leader));
+            anyout = anyout || ((FULL || y0 + i < ny) && !is_inlier(u[i][j], R) &&
+                                !(i == 0 && j == 0 && orow0 && leader));
     }
-    if (ballot(xin && anyout)) {
+    if (ballot((FULL || xin) && anyout)) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            if (y0 + i >= ny) continue;  // uniform
-            stage_row_outliers<V>(a, st.rank, w, u[i], xin, i == 0 && orow0 && leader,
+            if (!FULL && y0 + i >= ny) continue;  // uniform
+            stage_row_outliers<V>(a, st.rank, w, u[i], FULL || xin, i == 0 && orow0 && leader,
                                   ((uint64_t)z * ny + y0 + i) * nx, x0, gmask, blk);
         }
     }
@@ -394,6 +401,47 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
                                                            gpad, tile_total);
                 }
             }
+        } else if (C::NBT * C::NBR <= kMaxUnrollRows && (tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny &&
+                   (bz + 1) * C::BZ <= nz) {
+            // Interior tile: every block complete. The block row is one
+            // straight-line sequence of NBT batches with kPipeDepth batches
+            // of loads in flight ahead of the one being computed; loads and
+            // code stores are unconditional and addressed from wave-uniform
+            // row bases, so each wait retires exactly the batch it needs.
+            constexpr int NBT = C::NBT;
+            constexpr int D = cmin(NBT, kPipeDepth);
+            constexpr int YB = C::BY / C::NBR;  // batches per plane
+            const uint32_t voff = (uint32_t)lane * V;
+            for (int ch = 0; ch < C::XCH; ++ch) {
+                const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
+                const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                const uint32_t x0 = bx0 * B + voff;
+                const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
+                const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
+                const float* xb = a.x + base;
+                uint16_t* cb = a.codes + base;
+                EncState<DIM, B, V> st;
+                st.init();
+                float buf[D][C::NBR][V];
+                auto load = [&](auto bI, float (&bb)[C::NBR][V]) {
+                    constexpr int b = decltype(bI)::value;
+                    const float* p = xb + ((uint64_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
+#pragma unroll
+                    for (int i = 0; i < C::NBR; ++i) load_f<V>(p + (uint64_t)i * nx + voff, bb[i]);
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
+                static_for<0, NBT>([&](auto bI) {
+                    constexpr int b = decltype(bI)::value;
+                    constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
+                    enc_batch<DIM, B, V, C::NBR, true>(a, st, w, buf[b % D], zl, yb, bz * B + zl, by * C::BY + yb,
+                                                       x0, true, leader, gmask, blk, r, twoeb, eb, bad,
+                                                       cb + ((uint64_t)zl * ny + yb) * nx);
+                    if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
+                });
+                tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, by, bz, blk, x0, true, leader, gpad,
+                                                       tile_total);
+            }
         } else {
             for (int ch = 0; ch < C::XCH; ++ch) {
                 const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
@@ -421,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
                     __builtin_amdgcn_sched_barrier(0);
                 };
                 auto compute_batch = [&](int zl, int yb, float (&buf)[C::NBR][V]) {
-                    enc_batch<DIM, B, V, C::NBR>(a, st, w, buf, zl, yb, bz * B + zl, by * B + yb, x0, xin,
+                    enc_batch<DIM, B, V, C::NBR, false>(a, st, w, buf, zl, yb, bz * B + zl, by * B + yb, x0, xin,
                                                  leader, gmask, blk, r, twoeb, eb, bad);
                 };
                 float bufA[C::NBR][V], bufB[C::NBR][V];
@@ -553,23 +601,28 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
     if (bad && lane == 0) __hip_atomic_store(a.status, ST_ERANGE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-#define DQ_ENC_CASE(D, BB, VV)                                              \
-    if (dim == D && block == BB && v == VV) {                               \
-        hipLaunchKernelGGL((k_encode<D, BB, VV>), grid, dim3(kThreads), 0, stream, a); \
-        return true;                                                        \
-    }
+#ifndef DQ_DIM
+#error "dq_encode.hip is compiled once per DQ_DIM (1, 2, 3)"
+#endif
 
-bool launch_encode(int dim, int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
-    DQ_CONFIGS(DQ_ENC_CASE)
+// instantiated only for the configurations of this object's dimensionality
+template <int D, int BB, int VV>
+static bool try_launch_encode(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
+    if constexpr (D == DQ_DIM) {
+        if (block == BB && v == VV) {
+            hipLaunchKernelGGL((k_encode<D, BB, VV>), grid, dim3(kThreads), 0, stream, a);
+            return true;
+        }
+    }
     return false;
 }
 
-#define DQ_BPT_CASE(D, BB, VV) \
-    if (dim == D && block == BB && v == VV) return Cfg<D, BB, VV>::BPT;
+#define DQ_ENC_CASE(D, BB, VV) \
+    if (try_launch_encode<D, BB, VV>(block, v, a, grid, stream)) return true;
 
-int tile_blocks(int dim, int block, int v) {
-    DQ_CONFIGS(DQ_BPT_CASE)
-    return 0;
+bool DQ_CAT(launch_encode_dim, DQ_DIM)(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
+    DQ_CONFIGS(DQ_ENC_CASE)
+    return false;
 }
 
 }  // namespace dq

@@ -27,11 +27,39 @@
 
 namespace dq {
 
-// Returns false when (dim, block, v) is not a built configuration.
-bool launch_encode(int dim, int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
-bool launch_decode(int dim, int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
+// The encode and decode sources are compiled once per dimensionality (macro
+// DQ_DIM = 1, 2, 3) so the instantiations build in parallel; each object
+// defines the launchers of its own dimensionality. They return false when
+// (block, v) is not a built configuration.
+bool launch_encode_dim1(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
+bool launch_encode_dim2(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
+bool launch_encode_dim3(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
+bool launch_decode_dim1(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
+bool launch_decode_dim2(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
+bool launch_decode_dim3(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
+
+inline bool launch_encode(int dim, int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
+    return dim == 1 ? launch_encode_dim1(block, v, a, grid, stream)
+         : dim == 2 ? launch_encode_dim2(block, v, a, grid, stream)
+         : dim == 3 ? launch_encode_dim3(block, v, a, grid, stream) : false;
+}
+inline bool launch_decode(int dim, int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
+    return dim == 1 ? launch_decode_dim1(block, v, a, grid, stream)
+         : dim == 2 ? launch_decode_dim2(block, v, a, grid, stream)
+         : dim == 3 ? launch_decode_dim3(block, v, a, grid, stream) : false;
+}
+
 // Blocks per tile along x of a configuration (0 if not built).
-int tile_blocks(int dim, int block, int v);
+#define DQ_BPT_CASE(D, BB, VV) \
+    if (dim == D && block == BB && v == VV) return Cfg<D, BB, VV>::BPT;
+inline int tile_blocks(int dim, int block, int v) {
+    DQ_CONFIGS(DQ_BPT_CASE)
+    return 0;
+}
+#undef DQ_BPT_CASE
+
+#define DQ_CAT_(a, b) a##b
+#define DQ_CAT(a, b) DQ_CAT_(a, b)
 
 struct AuxArgs {
     const float* x;
