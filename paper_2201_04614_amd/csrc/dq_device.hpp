@@ -324,16 +324,26 @@ __device__ __forceinline__ void store_f(float* p, const float (&v)[V]) {
     }
 }
 
+// Write-through store: a relaxed system-scope store (sc0 sc1) goes through
+// the L2 to memory while the kernel runs instead of waiting, dirty, for the
+// write-back at the end of the kernel; on the encode pattern it is faster
+// than both plain and nontemporal stores. It is an ordinary store otherwise:
+// no ordering is implied.
+template <typename T>
+__device__ __forceinline__ void store_wt(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // V uint16 codes, packed in 16-bit halves of 32-bit words
 template <int V>
 __device__ __forceinline__ void store_codes(uint16_t* p, const uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        __builtin_nontemporal_store((uint16_t)c[0], p);
+        store_wt(p, (uint16_t)c[0]);
     } else if constexpr (V == 2) {
-        __builtin_nontemporal_store(c[0] | (c[1] << 16), reinterpret_cast<uint32_t*>(p));
+        store_wt(reinterpret_cast<uint32_t*>(p), c[0] | (c[1] << 16));
     } else {
-        u32x2 w = {c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
-        __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(p));
+        const uint64_t w = (uint64_t)(c[0] | (c[1] << 16)) | ((uint64_t)(c[2] | (c[3] << 16)) << 32);
+        store_wt(reinterpret_cast<uint64_t*>(p), w);
     }
 }
 
