@@ -242,8 +242,14 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     if (hooks && hooks->ev_before) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_before), stream);
     if (!launch_encode(pl.dim, pl.B, pl.V, ea, grid, stream)) return DQ_ENOTSUP;
     if (hooks && hooks->ev_after) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_after), stream);
-    launch_scan_tiles(tiles, pl.g.n_tiles, sc, status, res, out_cap, stream);
-    if (cap > 0) launch_scatter(stage, (uint32_t)cap, sc, status, tiles, info, pl.g, out_idx, out_val, stream);
+    if (pl.g.n_tiles <= kPlaceTiles) {
+        launch_place(stage, (uint32_t)cap, sc, res, out_cap, tiles, pl.g.n_tiles, info, pl.g, out_idx, out_val,
+                     stream);
+    } else {
+        launch_scan_tiles(tiles, pl.g.n_tiles, sc, status, res, out_cap, stream);
+        if (cap > 0)
+            launch_scatter(stage, (uint32_t)cap, sc, status, tiles, info, pl.g, out_idx, out_val, stream);
+    }
     return check_launch();
 }
 

@@ -1,8 +1,9 @@
 // dq_aux.hip - small kernels around the encode/decode passes (gfx950).
 //
 //  compress:   init -> [REL] min/max pass + bound resolution -> [GLOBAL] sum
-//              of q -> encode -> scan of per-tile outlier counts -> scatter of
-//              the staged outliers into block-major order
+//              of q -> encode -> scan of per-tile outlier counts and scatter
+//              of the staged outliers into block-major order (one fused
+//              kernel up to kPlaceTiles tiles, two kernels beyond)
 //  decompress: init -> [n_out > 0] per-block start of the outlier list (and
 //              validation of its order) -> decode
 // Status words are written with plain stores of one error value; the only
@@ -340,6 +341,83 @@ void launch_scatter(const uint4* stage, uint32_t stage_cap, const Scalars* sc, c
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, stream, stage, stage_cap, sc, status,
                        tile_offset, block_info, g, out_idx, out_val);
+}
+
+// ------------------------------------------------------------------ fused scan + scatter
+
+// One kernel for fields of at most kPlaceTiles tiles: every workgroup that
+// has staged outliers to move computes the exclusive scan of the tile counts
+// in LDS itself (a few KB read from L2), then places its share of the staged
+// entries; workgroup 0 writes n_out and the capacity verdict. With no
+// outliers every workgroup but the first returns at once.
+__global__ __launch_bounds__(256) void k_place(const uint4* __restrict__ stage, uint32_t cap, const Scalars* sc,
+                                               ResultDev* res, uint64_t out_cap,
+                                               const uint32_t* __restrict__ tile_count, uint32_t n_tiles,
+                                               const uint32_t* __restrict__ block_info, Geom g,
+                                               uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
+    __shared__ uint32_t pre[kPlaceTiles];
+    __shared__ uint32_t wsum[4];
+    const uint32_t staged = sc->stage_count;
+    const uint32_t n = min(staged, cap);
+    const bool lead = blockIdx.x == 0;
+    if (lead && staged == 0) {
+        if (threadIdx.x == 0 && load_status(&res->status) == ST_OK) res->n_out = 0;
+        return;
+    }
+    if (!lead && blockIdx.x * blockDim.x >= n) return;
+    // exclusive scan of the tile counts: thread k owns K consecutive tiles
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t K = (n_tiles + 255) / 256;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t i = tid * K + k;
+        s += i < n_tiles ? tile_count[i] : 0u;
+    }
+    const uint32_t incl = wave_scan_incl(s, lane);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - s;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t i = tid * K + k;
+        if (i < n_tiles) {
+            pre[i] = run;
+            run += tile_count[i];
+        }
+    }
+    const uint64_t total = (uint64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (lead && tid == 0 && load_status(&res->status) == ST_OK) {
+        res->n_out = total;
+        if (total > out_cap) store_status(&res->status, ST_ECAPACITY);
+    }
+    __syncthreads();
+    if (total > out_cap || load_status(&res->status) != ST_OK) return;  // the list is incomplete anyway
+    for (uint32_t i = blockIdx.x * blockDim.x + tid; i < n; i += gridDim.x * blockDim.x) {
+        const uint4 e = stage[i];
+        const uint32_t b = e.z;
+        const uint32_t bx = b % g.nbx;
+        const uint32_t rest = b / g.nbx;
+        const uint32_t by = rest % g.nby;
+        const uint32_t bz = rest / g.nby;
+        const uint32_t t = (bz * g.nby + by) * g.ntx + bx / g.bpt;
+        const uint32_t info = block_info[b];
+        uint32_t pos = pre[t] + (info & ~kOriginFlag);
+        if (!(e.w & kOriginFlag)) pos += (info >> 31) + e.w;
+        if (pos < n) {
+            out_idx[pos] = e.x;
+            out_val[pos] = (int32_t)e.y;
+        }
+    }
+}
+
+void launch_place(const uint4* stage, uint32_t cap, const Scalars* sc, void* res, uint64_t out_cap,
+                  const uint32_t* tile_count, uint32_t n_tiles, const uint32_t* block_info, Geom g,
+                  uint32_t* out_idx, int32_t* out_val, hipStream_t stream) {
+    uint32_t blocks = (cap + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, stream, stage, cap, sc, (ResultDev*)res, out_cap,
+                       tile_count, n_tiles, block_info, g, out_idx, out_val);
 }
 
 // ------------------------------------------------------------------ decompress

@@ -79,6 +79,10 @@ void launch_scan_tiles(uint32_t* tile_count, uint32_t n_tiles, Scalars* sc, int3
 void launch_scatter(const uint4* stage, uint32_t stage_cap, const Scalars* sc, const int32_t* status,
                     const uint32_t* tile_offset, const uint32_t* block_info, Geom g, uint32_t* out_idx,
                     int32_t* out_val, hipStream_t stream);
+constexpr uint32_t kPlaceTiles = 8192;  // tiles the fused scan + scatter holds in LDS
+void launch_place(const uint4* stage, uint32_t cap, const Scalars* sc, void* res, uint64_t out_cap,
+                  const uint32_t* tile_count, uint32_t n_tiles, const uint32_t* block_info, Geom g,
+                  uint32_t* out_idx, int32_t* out_val, hipStream_t stream);
 void launch_decompress_init(void* res, uint64_t n_out, double eb, hipStream_t stream);
 void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
                   uint32_t* block_start, int32_t* status, hipStream_t stream);

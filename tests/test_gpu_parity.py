@@ -137,6 +137,17 @@ def test_error_statuses(ref):
     G.parity(ref, F.constant_field((50, 60), 2.5), 1e-3, "rel", 8, "zero", 512)  # EINVAL
 
 
+@pytest.mark.parametrize("R", [1, 64])
+def test_outlier_ordering_beyond_fused_tiles(ref, R):
+    """More than 8192 tiles: the outliers are ordered by the separate tile scan
+    and scatter kernels instead of the fused one (ragged 1-D field)."""
+    n = 9 * 1024 * 1024 + 7
+    x = F.uniform_field((n,), seed=11 + R, lo=-50.0, hi=50.0)
+    G.say(f"many tiles: n={n} R={R}")
+    c = G.parity(ref, x, 1e-3, "abs", 16, "block_mean", R)
+    assert c.n_out > 1000
+
+
 def test_capacity(ref):
     x = F.sinusoid_field((128, 128), seed=4)
     eb = 1e-5 * F.field_range(x)
