@@ -102,7 +102,9 @@ typedef struct {
     int32_t vec;
 } dq_params;
 
-/* Device-resident outcome of one call. */
+/* Device-resident outcome of one call, 8-byte aligned. status and reserved
+ * form one 64-bit word that the kernels update atomically; reserved holds a
+ * per-call tag of the library (its value has no meaning to the caller). */
 typedef struct {
     int32_t status;   /* dq_status */
     uint32_t reserved;

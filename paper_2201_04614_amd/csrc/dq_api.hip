@@ -2,6 +2,10 @@
 // layout and the launch sequence of dq_compress / dq_decompress.
 #include <math.h>
 #include <string.h>
+#include <time.h>
+#include <unistd.h>
+
+#include <atomic>
 
 #include "../../include/dq.h"
 #include "dq_kernels.hpp"
@@ -138,6 +142,21 @@ CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     return L;
 }
 
+// Tag of a decompress call (see status_init_tagged): distinct for every call
+// of the process, never 0, salted per process so that a result buffer left
+// over from another process is unlikely to carry the same tag.
+uint32_t next_tag() {
+    static std::atomic<uint32_t> counter{0};
+    static const uint32_t salt = [] {
+        const uint64_t t = (uint64_t)time(nullptr) ^ ((uint64_t)getpid() << 20) ^
+                           (uint64_t)reinterpret_cast<uintptr_t>(&counter);
+        return (uint32_t)(t ^ (t >> 32)) * 2654435761u;
+    }();
+    uint32_t tag = 0;
+    while (tag == 0) tag = (counter.fetch_add(1) + 1) * 2654435761u ^ salt;
+    return tag;
+}
+
 dq_status check_launch() {
     return hipGetLastError() == hipSuccess ? DQ_OK : DQ_EDEVICE;
 }
@@ -198,6 +217,7 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     uint64_t npads = 0;
     dq_pad_count(p, &npads);
     if (!x || !codes || !res || !ws) return DQ_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(res) % 8) != 0) return DQ_EINVAL;
     if (out_cap > 0 && (!out_idx || !out_val)) return DQ_EINVAL;
     if (npads > 0 && !pads) return DQ_EINVAL;
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return DQ_EINVAL;
@@ -217,15 +237,18 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
 
     uint4* parts = reinterpret_cast<uint4*>(w + L.parts);
     AuxArgs aa{x, sc, status, pl.g.N};
+    BoundArgs bound{parts, 0, p->eb};  // parts: read but unused for an absolute bound
     if (p->eb_mode == DQ_EB_REL) {
-        const int nparts = launch_minmax(aa, parts, stream);
-        launch_resolve_rel(sc, res, parts, nparts, p->eb, stream);  // also initialises the call
+        bound.parts = parts;
+        bound.nparts = launch_minmax(aa, parts, res, stream);  // also initialises the call
     } else {
         launch_compress_init(sc, res, p->eb, stream);
     }
-    if (p->pad_mode == DQ_PAD_GLOBAL_MEAN) launch_sumq(aa, stream);
+    if (p->pad_mode == DQ_PAD_GLOBAL_MEAN) launch_sumq(aa, bound, stream);
 
     EncArgs ea;
+    ea.bound = bound;
+    ea.eb_out = &res->eb_abs;
     ea.x = x;
     ea.codes = codes;
     ea.pads = pads;
@@ -263,6 +286,7 @@ dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes
     uint64_t npads = 0;
     dq_pad_count(p, &npads);
     if (!codes || !x_hat || !res) return DQ_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(res) % 8) != 0) return DQ_EINVAL;  // one 64-bit status word
     if (n_out > 0 && (!out_idx || !out_val || !ws)) return DQ_EINVAL;
     if (npads > 0 && !pads) return DQ_EINVAL;
     Plan pl;
@@ -274,19 +298,22 @@ dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     uint32_t* block_start = static_cast<uint32_t*>(ws);
-    int32_t* status = &res->status;
-    launch_decompress_init(res, n_out, eb_abs, stream);
+    const uint32_t tag = next_tag();
     if (n_out > 0)
-        launch_index(out_idx, (uint32_t)n_out, pl.g, ilog2((uint32_t)pl.B), pl.dim, block_start, status, stream);
+        launch_index(out_idx, (uint32_t)n_out, pl.g, ilog2((uint32_t)pl.B), pl.dim, block_start, res, tag, stream);
 
     DecArgs da;
+    da.res_word = reinterpret_cast<unsigned long long*>(res);
+    da.n_out_out = reinterpret_cast<unsigned long long*>(&res->n_out);
+    da.eb_out = &res->eb_abs;
+    da.eb_abs = eb_abs;
+    da.tag = tag;
     da.codes = codes;
     da.out_idx = out_idx;
     da.out_val = out_val;
     da.pads = pads;
     da.block_start = block_start;
     da.x_hat = x_hat;
-    da.status = status;
     da.g = pl.g;
     da.twoeb = 2.0 * eb_abs;
     da.n_out = (uint32_t)n_out;

@@ -1,11 +1,13 @@
 // dq_aux.hip - small kernels around the encode/decode passes (gfx950).
 //
-//  compress:   init -> [REL] min/max pass + bound resolution -> [GLOBAL] sum
-//              of q -> encode -> scan of per-tile outlier counts and scatter
+//  compress:   [ABS] init | [REL] min/max pass (which initialises the call;
+//              the consuming kernels resolve the bound per workgroup) ->
+//              [GLOBAL] sum of q -> encode -> scan of per-tile outlier counts and scatter
 //              of the staged outliers into block-major order (one fused
 //              kernel up to kPlaceTiles tiles, two kernels beyond)
-//  decompress: init -> [n_out > 0] per-block start of the outlier list (and
-//              validation of its order) -> decode
+//  decompress: [n_out > 0] per-block start of the outlier list (and
+//              validation of its order) -> decode (which also initialises the
+//              call's result)
 // Status words are written with plain stores of one error value; the only
 // device errors of a compress call are EINVAL/ERANGE (before or during encode)
 // and ECAPACITY (decided by the scan when no other error occurred); decode
@@ -57,16 +59,6 @@ void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream)
 
 // ------------------------------------------------------------------ value range (REL bound)
 
-// order-preserving map of a finite float to uint32
-__device__ __forceinline__ uint32_t fkey(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float funkey(uint32_t k) {
-    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
-    return __uint_as_float(u);
-}
-
 __device__ __forceinline__ void minmax_acc(float e, uint32_t& kmin, uint32_t& kmax, bool& nf) {
     const bool fin = __builtin_isfinite(e);
     nf |= !fin;
@@ -75,10 +67,18 @@ __device__ __forceinline__ void minmax_acc(float e, uint32_t& kmin, uint32_t& km
     kmax = fin ? max(kmax, k) : kmax;
 }
 
-// Per-workgroup min / max keys and a non-finite flag (no atomics: the
-// partials are combined by k_resolve_rel).
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N, uint4* parts, int vec4) {
-    __shared__ uint32_t smin[4], smax[4], snf[4];
+// Per-workgroup min / max keys and a non-finite flag (no atomics: every
+// wave of the kernels that need the bound combines the partials, see
+// bound_finish). First kernel of a compress call with a relative bound, so
+// it also initialises the call.
+__global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restrict__ x, uint64_t N, uint4* parts,
+                                                           int vec4, Scalars* sc, ResultDev* res) {
+    constexpr int W = kMinmaxThreads / 64;
+    __shared__ uint32_t smin[W], smax[W], snf[W];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        init_scalars(sc, res);
+        res->eb_abs = 0.0;
+    }
     uint32_t kmin = 0xffffffffu, kmax = 0u;
     bool nf = false;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
     __syncthreads();
     if (threadIdx.x == 0) {
         uint4 pr = make_uint4(smin[0], smax[0], snf[0], 0u);
-        for (int w = 1; w < 4; ++w) {
+        for (int w = 1; w < W; ++w) {
             pr.x = min(pr.x, smin[w]);
             pr.y = max(pr.y, smax[w]);
             pr.z |= snf[w];
@@ -134,80 +134,28 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
     }
 }
 
-int launch_minmax(const AuxArgs& a, uint4* parts, hipStream_t stream) {
+int launch_minmax(const AuxArgs& a, uint4* parts, void* res, hipStream_t stream) {
     const int vec4 = ((reinterpret_cast<uintptr_t>(a.x) & 15u) == 0) ? 1 : 0;
     uint64_t work = vec4 ? a.N / 4 : a.N;
-    uint64_t blocks = (work + 1023) / 1024;
+    uint64_t blocks = (work + 4 * kMinmaxThreads - 1) / (4 * kMinmaxThreads);
     if (blocks > kMinmaxParts) blocks = kMinmaxParts;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_minmax, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, parts, vec4);
+    hipLaunchKernelGGL(k_minmax, dim3((uint32_t)blocks), dim3(kMinmaxThreads), 0, stream, a.x, a.N, parts, vec4,
+                       a.sc, (ResultDev*)res);
     return (int)blocks;
-}
-
-// Initialises the call's scalars and resolves the relative bound
-// (Section II-B, value-range relative): eb = rel * (max - min).
-__global__ __launch_bounds__(1024) void k_resolve_rel(Scalars* sc, ResultDev* res, const uint4* parts,
-                                                      int nparts, double rel) {
-    __shared__ uint32_t smin[16], smax[16], snf[16];
-    uint32_t kmin = 0xffffffffu, kmax = 0u, nf = 0u;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        const uint4 pr = parts[i];
-        kmin = min(kmin, pr.x);
-        kmax = max(kmax, pr.y);
-        nf |= pr.z;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
-        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
-        nf |= (uint32_t)__shfl_xor((int)nf, off);
-    }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        smin[wave] = kmin;
-        smax[wave] = kmax;
-        snf[wave] = nf;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-        kmin = min(kmin, smin[w]);
-        kmax = max(kmax, smax[w]);
-        nf |= snf[w];
-    }
-    init_scalars(sc, res);
-    sc->eb = sc->twoeb = sc->r = 0.0;
-    res->eb_abs = 0.0;
-    if (nf) {
-        res->status = ST_ERANGE;
-        return;
-    }
-    const double mn = (double)funkey(kmin);
-    const double mx = (double)funkey(kmax);
-    const double eb = rel * (mx - mn);
-    const double r = 1.0 / (2.0 * eb);
-    if (!(eb > 0.0) || !__builtin_isfinite(eb) || !__builtin_isfinite(r)) {
-        res->status = ST_EINVAL;
-        return;
-    }
-    sc->eb = eb;
-    sc->twoeb = 2.0 * eb;
-    sc->r = r;
-    res->eb_abs = eb;
-}
-
-void launch_resolve_rel(Scalars* sc, void* res, const uint4* parts, int nparts, double rel, hipStream_t stream) {
-    hipLaunchKernelGGL(k_resolve_rel, dim3(1), dim3(1024), 0, stream, sc, (ResultDev*)res, parts, nparts, rel);
 }
 
 // ------------------------------------------------------------------ global mean of q
 
 __global__ __launch_bounds__(256) void k_sumq(const float* __restrict__ x, uint64_t N, Scalars* sc,
-                                              int32_t* status) {
+                                              int32_t* status, BoundArgs bound) {
     __shared__ long long ssum[4];
     __shared__ int sbad[4];
-    if (load_status(status) != ST_OK) return;
-    const double r = sc->r, twoeb = sc->twoeb, eb = sc->eb;
+    uint4 pp[kBoundPer];
+    bound_fetch(bound, pp, threadIdx.x & 63);
+    const Bound bd = bound_finish(bound, pp, threadIdx.x & 63);  // an invalid bound is reported by encode
+    if (bd.status != ST_OK || load_status(status) != ST_OK) return;
+    const double r = bd.r, twoeb = bd.twoeb, eb = bd.eb;
     long long s = 0;
     uint64_t bad = 0;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,11 +185,11 @@ __global__ __launch_bounds__(256) void k_sumq(const float* __restrict__ x, uint6
     }
 }
 
-void launch_sumq(const AuxArgs& a, hipStream_t stream) {
+void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream) {
     uint64_t blocks = (a.N + 1023) / 1024;
     if (blocks > 512) blocks = 512;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_sumq, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, a.status);
+    hipLaunchKernelGGL(k_sumq, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, a.status, bound);
 }
 
 // ------------------------------------------------------------------ scan of tile counts
@@ -422,19 +370,6 @@ void launch_place(const uint4* stage, uint32_t cap, const Scalars* sc, void* res
 
 // ------------------------------------------------------------------ decompress
 
-__global__ void k_decompress_init(ResultDev* res, unsigned long long n_out, double eb) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    res->status = ST_OK;
-    res->reserved = 0;
-    res->n_out = n_out;
-    res->eb_abs = eb;
-}
-
-void launch_decompress_init(void* res, uint64_t n_out, double eb, hipStream_t stream) {
-    hipLaunchKernelGGL(k_decompress_init, dim3(1), dim3(64), 0, stream, (ResultDev*)res,
-                       (unsigned long long)n_out, eb);
-}
-
 struct IndexGeom {
     Geom g;
     uint32_t lb;   // log2 B
@@ -455,7 +390,7 @@ __device__ __forceinline__ void cell_block(const IndexGeom& ig, uint32_t idx, ui
 // outliers must be in strictly increasing (block, local row-major) order.
 __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_idx, uint32_t n_out,
                                                IndexGeom ig, uint32_t* __restrict__ block_start,
-                                               int32_t* status) {
+                                               unsigned long long* res_word, uint32_t tag) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t N = ig.g.N;
     if (i < n_out) {
@@ -472,7 +407,7 @@ __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_
                 ok = (b0 < b1) || (b0 == b1 && l0 < l1);
             }
         }
-        if (!ok) store_status(status, ST_ECORRUPT);
+        if (!ok) status_corrupt_tagged(res_word, tag);
     }
     if (i <= ig.g.nblocks) {
         uint32_t lo = 0, hi = n_out;
@@ -489,11 +424,12 @@ __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_
 }
 
 void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
-                  uint32_t* block_start, int32_t* status, hipStream_t stream) {
+                  uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream) {
     IndexGeom ig{g, (uint32_t)block_log2, (uint32_t)dim};
     const uint64_t work = n_out > (uint64_t)g.nblocks + 1 ? (uint64_t)n_out : (uint64_t)g.nblocks + 1;
     const uint32_t blocks = (uint32_t)((work + 255) / 256);
-    hipLaunchKernelGGL(k_index, dim3(blocks), dim3(256), 0, stream, out_idx, n_out, ig, block_start, status);
+    hipLaunchKernelGGL(k_index, dim3(blocks), dim3(256), 0, stream, out_idx, n_out, ig, block_start,
+                       reinterpret_cast<unsigned long long*>(res), tag);
 }
 
 }  // namespace dq

@@ -191,9 +191,6 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
     }
 }
 
-__device__ __forceinline__ void mark_corrupt(int32_t* status) {
-    __hip_atomic_store(status, ST_ECORRUPT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <int DIM, int B, int V>
 __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
@@ -201,6 +198,11 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kWaves + wave;
+    if (t == 0 && lane == 0) {  // the call's result (status: see status_init_tagged)
+        *a.n_out_out = a.n_out;
+        *a.eb_out = a.eb_abs;
+        status_init_tagged(a.res_word, a.tag);
+    }
     if (t >= a.g.n_tiles) return;
     const uint32_t tx = t % a.g.ntx;
     const uint32_t rr = t / a.g.ntx;
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
             if (lane == 0 && rank != oe - os) corrupt = true;
         }
     }
-    if (ballot(corrupt) && lane == 0) mark_corrupt(a.status);
+    if (ballot(corrupt) && lane == 0) status_corrupt_tagged(a.res_word, a.tag);
 }
 
 #ifndef DQ_DIM

@@ -99,7 +99,19 @@ struct Scalars {
     int gpad;                  // global pad value
 };
 
+// The error bound of a compress call as the kernels receive it: either the
+// absolute bound itself, or the relative factor and the per-workgroup
+// partials of the value-range pass (min key, max key, non-finite flag), which
+// each workgroup of the consuming kernel reduces itself.
+struct BoundArgs {
+    const uint4* parts;  // always a valid address of kBoundParts entries
+    int nparts;          // 0: v is the absolute bound
+    double v;            // absolute bound, or the relative factor
+};
+
 struct EncArgs {
+    BoundArgs bound;
+    double* eb_out;        // dq_result.eb_abs (written for a relative bound)
     const float* x;
     uint16_t* codes;
     int32_t* pads;
@@ -114,14 +126,38 @@ struct EncArgs {
     int32_t pad_mode;
 };
 
+// Status of a decompress call, initialised by the decode kernel itself: the
+// first 8 bytes of dq_result (status, reserved) form one word whose upper
+// half carries the call's tag. Tile 0 sets (tag, OK) unless the word already
+// holds this call's tag; a corruption report sets (tag, ECORRUPT)
+// unconditionally. Either order leaves ECORRUPT if any report was made.
+__device__ __forceinline__ void status_init_tagged(unsigned long long* w, uint32_t tag) {
+    unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long ok = ((unsigned long long)tag << 32) | (uint32_t)ST_OK;
+    while ((uint32_t)(old >> 32) != tag) {
+        if (__hip_atomic_compare_exchange_strong(w, &old, ok, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            break;
+    }
+}
+
+__device__ __forceinline__ void status_corrupt_tagged(unsigned long long* w, uint32_t tag) {
+    (void)__hip_atomic_exchange(w, ((unsigned long long)tag << 32) | (uint32_t)ST_ECORRUPT, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct DecArgs {
+    unsigned long long* res_word;  // dq_result status + reserved (tagged, see above)
+    unsigned long long* n_out_out; // dq_result.n_out
+    double* eb_out;                // dq_result.eb_abs
+    double eb_abs;
+    uint32_t tag;
     const uint16_t* codes;
     const uint32_t* out_idx;
     const int32_t* out_val;
     const int32_t* pads;
     const uint32_t* block_start;  // n_blocks + 1 entries (unused when n_out == 0)
     float* x_hat;
-    int32_t* status;
     Geom g;
     double twoeb;
     uint32_t n_out;
@@ -154,6 +190,11 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
 // a value every lane holds identically, kept in a scalar register
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ double uniform(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = uniform((uint32_t)u), hi = uniform((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
 }
 
 // Inclusive prefix sum of v over aligned segments of G lanes (G power of 2).
@@ -290,6 +331,79 @@ __device__ __forceinline__ void prequant(const float (&x)[V], double r, double t
     }
 #pragma unroll
     for (int j = 0; j < V; ++j) q[j] = (uint32_t)(int32_t)k[j];
+}
+
+// ------------------------------------------------------------------ error bound
+
+// order-preserving map of a finite float to uint32, and back
+__device__ __forceinline__ uint32_t fkey(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float funkey(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+struct Bound {
+    double eb, twoeb, r;
+    int status;  // ST_OK, ST_ERANGE (non-finite input), ST_EINVAL (zero value range)
+};
+
+// At most kBoundParts value-range partials (the value-range pass launches at
+// most that many workgroups), read by a wave as kBoundParts / 64 per lane.
+constexpr int kBoundParts = 256;
+constexpr int kBoundPer = kBoundParts / 64;
+
+// Issue the loads of the partials (every lane loads, from a valid address
+// even for an absolute bound, so no path skips them); bound_finish waits.
+__device__ __forceinline__ void bound_fetch(const BoundArgs& b, uint4 (&pp)[kBoundPer], int lane) {
+#pragma unroll
+    for (int k = 0; k < kBoundPer; ++k) {
+        const int i = lane + 64 * k;
+        pp[k] = b.parts[i < b.nparts ? i : 0];
+    }
+}
+
+// The absolute bound, resolved for a relative one (Section II-B, value-range
+// relative bound): eb = rel * (max - min) over the finite inputs. Wave-wide
+// (no barrier); every lane gets the same result.
+__device__ __forceinline__ Bound bound_finish(const BoundArgs& b, const uint4 (&pp)[kBoundPer], int lane) {
+    Bound o;
+    o.status = ST_OK;
+    if (b.nparts == 0) {
+        o.eb = b.v;
+    } else {
+        uint32_t kmin = 0xffffffffu, kmax = 0u, nf = 0u;
+#pragma unroll
+        for (int k = 0; k < kBoundPer; ++k) {
+            const bool in = lane + 64 * k < b.nparts;
+            kmin = in ? min(kmin, pp[k].x) : kmin;
+            kmax = in ? max(kmax, pp[k].y) : kmax;
+            nf |= in ? pp[k].z : 0u;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+            nf |= (uint32_t)__shfl_xor((int)nf, off);
+        }
+        const double mn = (double)funkey(kmin);
+        const double mx = (double)funkey(kmax);
+        o.eb = b.v * (mx - mn);
+        if (nf) {
+            o.status = ST_ERANGE;
+        } else if (!(o.eb > 0.0) || !__builtin_isfinite(o.eb) || !__builtin_isfinite(1.0 / (2.0 * o.eb))) {
+            o.status = ST_EINVAL;
+        }
+    }
+    if (o.status != ST_OK) o.eb = 0.0;
+    o.eb = uniform(o.eb);  // wave-uniform: keep the bound in scalar registers
+    o.status = (int)uniform((uint32_t)o.status);
+    o.twoeb = 2.0 * o.eb;
+    o.r = o.status == ST_OK ? 1.0 / (2.0 * o.eb) : 0.0;
+    o.r = uniform(o.r);
+    return o;
 }
 
 // ------------------------------------------------------------------ vector memory

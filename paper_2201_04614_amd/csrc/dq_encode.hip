@@ -351,12 +351,20 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
     const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kWaves + wave;
     if (t >= a.g.n_tiles) return;
-    if (__builtin_nontemporal_load(a.status) != ST_OK) {
+    // the bound: every wave reduces the value-range partials itself
+    uint4 pp[kBoundPer];
+    bound_fetch(a.bound, pp, lane);
+    const Bound bd = bound_finish(a.bound, pp, lane);
+    if (a.bound.nparts && t == 0 && lane == 0) {
+        *a.eb_out = bd.eb;
+        if (bd.status != ST_OK) __hip_atomic_store(a.status, bd.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (bd.status != ST_OK || __builtin_nontemporal_load(a.status) != ST_OK) {
         if (lane == 0) a.tile_count[t] = 0;
         return;
     }
     WaveCtx w{sbuf_all[wave], 0u, lane};
-    const double r = a.sc->r, twoeb = a.sc->twoeb, eb = a.sc->eb;
+    const double r = bd.r, twoeb = bd.twoeb, eb = bd.eb;
     uint32_t gpad = 0;
     if (a.pad_mode == PAD_GLOBAL) {
         gpad = (uint32_t)round_mean((long long)a.sc->sumq, (long long)a.g.N);

@@ -68,12 +68,12 @@ struct AuxArgs {
     uint64_t N;
 };
 
-constexpr int kMinmaxParts = 1024;  // value-range partials (one per workgroup)
+constexpr int kMinmaxParts = kBoundParts;  // value-range partials (one per workgroup)
+constexpr int kMinmaxThreads = 1024;
 
 void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream);
-int launch_minmax(const AuxArgs& a, uint4* parts, hipStream_t stream);
-void launch_resolve_rel(Scalars* sc, void* res, const uint4* parts, int nparts, double rel, hipStream_t stream);
-void launch_sumq(const AuxArgs& a, hipStream_t stream);
+int launch_minmax(const AuxArgs& a, uint4* parts, void* res, hipStream_t stream);
+void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream);
 void launch_scan_tiles(uint32_t* tile_count, uint32_t n_tiles, Scalars* sc, int32_t* status, void* res,
                        uint64_t out_cap, hipStream_t stream);
 void launch_scatter(const uint4* stage, uint32_t stage_cap, const Scalars* sc, const int32_t* status,
@@ -83,8 +83,7 @@ constexpr uint32_t kPlaceTiles = 8192;  // tiles the fused scan + scatter holds 
 void launch_place(const uint4* stage, uint32_t cap, const Scalars* sc, void* res, uint64_t out_cap,
                   const uint32_t* tile_count, uint32_t n_tiles, const uint32_t* block_info, Geom g,
                   uint32_t* out_idx, int32_t* out_val, hipStream_t stream);
-void launch_decompress_init(void* res, uint64_t n_out, double eb, hipStream_t stream);
 void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
-                  uint32_t* block_start, int32_t* status, hipStream_t stream);
+                  uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream);
 
 }  // namespace dq
