@@ -95,21 +95,27 @@ bool make_plan(const dq_params* p, const void* fptr, const void* cptr, Plan& pl)
         const int V = p->vec;
         if ((fa % (4u * V)) == 0 && (ca % (2u * V)) == 0 && finish_plan(p, V, pl)) return true;
     }
-    // Automatic: the widest vector that still gives every SIMD of the chip
-    // (256 CUs x 4) at least two waves; otherwise the one with most tiles.
-    constexpr uint32_t kWaveTarget = 2048;
+    // Automatic: the vector width that keeps the most waves resident on every
+    // SIMD, min(encode occupancy, tiles per SIMD); ties go to the wider one
+    // (fewer instructions per cell).
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
     bool found = false;
+    double best = -1.0;
     for (int V = 4; V >= 1; V >>= 1) {
         if ((fa % (4u * V)) != 0 || (ca % (2u * V)) != 0) continue;
         Plan cand;
         if (!finish_plan(p, V, cand)) continue;
-        if (!found || cand.g.n_tiles > pl.g.n_tiles) {
+        int occ = encode_occupancy(p->ndim, p->block, V);
+        if (occ < 1) occ = 1;
+        const double per_simd = (double)cand.g.n_tiles / (4.0 * cus);
+        const double resident = per_simd < occ ? per_simd : (double)occ;
+        if (!found || resident > best) {
             pl = cand;
+            best = resident;
             found = true;
-        }
-        if (cand.g.n_tiles >= kWaveTarget) {
-            pl = cand;
-            return true;
         }
     }
     return found;

@@ -130,12 +130,13 @@ __device__ __forceinline__ void dec_row(const DecArgs& a, DecState<DIM, B, V>& s
 // A batch of NR consecutive rows (local rows yb .. yb+NR-1 of local plane zl)
 // of a 2-D/3-D step: the outlier lookup is entered once per batch by the
 // whole wave, the prefix sums and dequantisation are branch-free across rows.
-// FULL: every row and lane lies inside the field; row i is written to
-// orow + i*nx + lane*V (orow is wave-uniform) with no per-lane condition.
+// FULL: every row and lane lies inside the field; row i is written through
+// the tile's buffer resource ors at scalar offset osoff + i*nx*4, with no
+// per-lane condition.
 template <int DIM, int B, int V, int NR, bool FULL>
 __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[NR][V],
                                           int yb, uint32_t z, uint32_t y0, uint32_t x0, bool xin, uint64_t gmask,
-                                          int lane, bool& corrupt, float* orow = nullptr) {
+                                          int lane, bool& corrupt, Rsrc ors = Rsrc(), uint32_t osoff = 0) {
     using C = Cfg<DIM, B, V>;
     const uint32_t R = (uint32_t)a.R;
     const uint32_t ny = a.g.ny, nx = a.g.nx;
@@ -185,7 +186,7 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
             o[j] = (float)((double)q * a.twoeb);
         }
         if constexpr (FULL)
-            store_f<V>(orow + (uint64_t)i * nx + (uint32_t)(lane * V), o);
+            store_f_buf<V>(ors, (uint32_t)(lane * V * 4), osoff + (uint32_t)i * nx * 4u, o);
         else if (xin && y0 + i < ny)
             store_f<V>(a.x_hat + ((uint64_t)z * ny + y0 + i) * nx + x0, o);
     }
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
                 }
             }
         } else if (C::NBT * C::NBR <= kMaxUnrollRows && (tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny &&
-                   (bz + 1) * C::BZ <= nz) {
+                   (bz + 1) * C::BZ <= nz && (uint64_t)((C::BZ - 1) * ny + C::BY) * nx * 4u < 0x7fffffffull) {
             // Interior tile: the block row is one straight-line sequence of
             // NBT batches with kPipeDepth batches of loads in flight ahead of
             // the one being decoded; loads and stores are unconditional and
@@ -254,16 +255,17 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
                 const uint32_t x0 = bx0 * B + voff;
                 const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
                 const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
-                const uint16_t* cb = a.codes + base;
-                float* ob = a.x_hat + base;
+                const Rsrc crs = make_rsrc(a.codes + base);
+                const Rsrc ors = make_rsrc(a.x_hat + base);
                 DecState<DIM, B, V> st;
                 st.init(a, blk, true);
                 uint32_t buf[D][C::NBR][V];
                 auto load = [&](auto bI, uint32_t (&bb)[C::NBR][V]) {
                     constexpr int b = decltype(bI)::value;
-                    const uint16_t* p = cb + ((uint64_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
+                    const uint32_t row0 = ((uint32_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
 #pragma unroll
-                    for (int i = 0; i < C::NBR; ++i) load_codes<V>(p + (uint64_t)i * nx + voff, bb[i]);
+                    for (int i = 0; i < C::NBR; ++i)
+                        load_codes_buf<V>(crs, voff * 2u, (row0 + (uint32_t)i * nx) * 2u, bb[i]);
                     __builtin_amdgcn_sched_barrier(0);
                 };
                 static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
@@ -271,8 +273,8 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
                     constexpr int b = decltype(bI)::value;
                     constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
                     dec_batch<DIM, B, V, C::NBR, true>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb, x0,
-                                                       true, gmask, lane, corrupt,
-                                                       ob + ((uint64_t)zl * ny + yb) * nx);
+                                                       true, gmask, lane, corrupt, ors,
+                                                       ((uint32_t)zl * ny + yb) * nx * 4u);
                     if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
                 });
                 if (leader && st.rank != st.oe - st.os) corrupt = true;

@@ -474,6 +474,85 @@ __device__ __forceinline__ void load_codes(const uint16_t* p, uint32_t (&c)[V]) 
     }
 }
 
+// ------------------------------------------------------------------ buffer addressing
+//
+// Interior tiles address their rows through one buffer resource per tile
+// (base = the tile's first cell): the row offset is a scalar (soffset) and
+// the lane offset one vector register shared by every row, instead of one
+// 64-bit address per row. Raw buffer, 32-bit data format, no bounds beyond
+// 2^31 - 1 bytes (the interior path requires the tile to span less).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcFlags = 0x00020000;
+constexpr int kPolNT = 2;   // nontemporal
+constexpr int kPolWT = 17;  // sc0 sc1: write-through (see store_wt)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, kRsrcFlags);
+}
+
+template <int V>
+__device__ __forceinline__ void load_f_buf(Rsrc rs, uint32_t voff, uint32_t soff, float (&v)[V]) {
+    if constexpr (V == 1) {
+        v[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, kPolNT));
+    } else if constexpr (V == 2) {
+        // reinterpret the whole vector as floats: splitting it into integer
+        // lanes first made this compiler keep only the first dword of the load
+        const f32x2 t = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, kPolNT));
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        const f32x4 t = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, kPolNT));
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_f_buf(Rsrc rs, uint32_t voff, uint32_t soff, const float (&v)[V]) {
+    if constexpr (V == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[0]), rs, (int)voff, (int)soff, kPolNT);
+    } else if constexpr (V == 2) {
+        const u32x2 t = {__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1])};
+        __builtin_amdgcn_raw_buffer_store_b64(t, rs, (int)voff, (int)soff, kPolNT);
+    } else {
+        const u32x4 t = {__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1]),
+                         __builtin_bit_cast(uint32_t, v[2]), __builtin_bit_cast(uint32_t, v[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(t, rs, (int)voff, (int)soff, kPolNT);
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_codes_buf(Rsrc rs, uint32_t voff, uint32_t soff, const uint32_t (&c)[V]) {
+    if constexpr (V == 1) {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)c[0], rs, (int)voff, (int)soff, kPolWT);
+    } else if constexpr (V == 2) {
+        __builtin_amdgcn_raw_buffer_store_b32(c[0] | (c[1] << 16), rs, (int)voff, (int)soff, kPolWT);
+    } else {
+        const u32x2 w = {c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
+        __builtin_amdgcn_raw_buffer_store_b64(w, rs, (int)voff, (int)soff, kPolWT);
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void load_codes_buf(Rsrc rs, uint32_t voff, uint32_t soff, uint32_t (&c)[V]) {
+    if constexpr (V == 1) {
+        c[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)voff, (int)soff, kPolNT);
+    } else if constexpr (V == 2) {
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, kPolNT);
+        c[0] = w & 0xffffu;
+        c[1] = w >> 16;
+    } else {
+        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, kPolNT));
+        c[0] = w.x & 0xffffu;
+        c[1] = w.x >> 16;
+        c[2] = w.y & 0xffffu;
+        c[3] = w.y >> 16;
+    }
+}
+
 // Write a wave's staged outliers (LDS) to the global staging list.
 __device__ __forceinline__ void flush_stage(uint4* sbuf, uint32_t n, uint4* stage, uint32_t cap,
                                             unsigned int* counter, int lane) {

@@ -174,14 +174,15 @@ __device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& s
 
 // A batch of NR consecutive rows (local rows yb .. yb+NR-1 of local plane zl)
 // of a 2-D/3-D step. FULL: every row and lane lies inside the field; the
-// codes of row i go to crow + i*nx + lane*V (crow is wave-uniform), with no
-// per-lane condition, so every store is issued on every path.
+// codes of row i are stored through the tile's buffer resource crs at
+// scalar offset csoff + i*nx*2, with no per-lane condition, so every store
+// is issued on every path.
 template <int DIM, int B, int V, int NR, bool FULL>
 __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
                                           const float (&xv)[NR][V], int zl, int yb, uint32_t z, uint32_t y0,
                                           uint32_t x0, bool xin, bool leader, uint64_t gmask, uint32_t blk,
                                           double r, double twoeb, double eb, uint64_t& bad,
-                                          uint16_t* crow = nullptr) {
+                                          Rsrc crs = Rsrc(), uint32_t csoff = 0) {
     const uint32_t R = (uint32_t)a.R;
     const uint32_t ny = a.g.ny, nx = a.g.nx;
     // phase 1: pre-quantisation of every row
@@ -228,7 +229,7 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
             for (int j = 0; j < V; ++j) st.dcode[j] = code[j];
         }
         if constexpr (FULL)
-            store_codes<V>(crow + (uint64_t)i * nx + (uint32_t)(w.lane * V), code);
+            store_codes_buf<V>(crs, (uint32_t)(w.lane * V * 2), csoff + (uint32_t)i * nx * 2u, code);
         else if (xin && y0 + i < ny)
             store_codes<V>(a.codes + ((uint64_t)z * ny + y0 + i) * nx + x0, code);
     }
@@ -343,8 +344,10 @@ __device__ __forceinline__ uint32_t enc_block_end(const EncArgs& a, EncState<DIM
     return step_total;
 }
 
+// One value per lane (V = 1) gives twice the tiles of V = 2; the register
+// budget is capped so that four waves fit on every SIMD.
 template <int DIM, int B, int V>
-__global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
+__global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a) {
     using C = Cfg<DIM, B, V>;
     __shared__ uint4 sbuf_all[kWaves][kStageCap];
     const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
                 }
             }
         } else if (C::NBT * C::NBR <= kMaxUnrollRows && (tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny &&
-                   (bz + 1) * C::BZ <= nz) {
+                   (bz + 1) * C::BZ <= nz && (uint64_t)((C::BZ - 1) * ny + C::BY) * nx * 4u < 0x7fffffffull) {
             // Interior tile: every block complete. The block row is one
             // straight-line sequence of NBT batches with kPipeDepth batches
             // of loads in flight ahead of the one being computed; loads and
@@ -426,16 +429,16 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
                 const uint32_t x0 = bx0 * B + voff;
                 const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
                 const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
-                const float* xb = a.x + base;
-                uint16_t* cb = a.codes + base;
+                const Rsrc xrs = make_rsrc(a.x + base);
+                const Rsrc crs = make_rsrc(a.codes + base);
                 EncState<DIM, B, V> st;
                 st.init();
                 float buf[D][C::NBR][V];
                 auto load = [&](auto bI, float (&bb)[C::NBR][V]) {
                     constexpr int b = decltype(bI)::value;
-                    const float* p = xb + ((uint64_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
+                    const uint32_t row0 = ((uint32_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
 #pragma unroll
-                    for (int i = 0; i < C::NBR; ++i) load_f<V>(p + (uint64_t)i * nx + voff, bb[i]);
+                    for (int i = 0; i < C::NBR; ++i) load_f_buf<V>(xrs, voff * 4u, (row0 + (uint32_t)i * nx) * 4u, bb[i]);
                     __builtin_amdgcn_sched_barrier(0);
                 };
                 static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
@@ -443,8 +446,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncArgs a) {
                     constexpr int b = decltype(bI)::value;
                     constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
                     enc_batch<DIM, B, V, C::NBR, true>(a, st, w, buf[b % D], zl, yb, bz * B + zl, by * C::BY + yb,
-                                                       x0, true, leader, gmask, blk, r, twoeb, eb, bad,
-                                                       cb + ((uint64_t)zl * ny + yb) * nx);
+                                                       x0, true, leader, gmask, blk, r, twoeb, eb, bad, crs,
+                                                       ((uint32_t)zl * ny + yb) * nx * 2u);
                     if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
                 });
                 tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, by, bz, blk, x0, true, leader, gpad,
@@ -631,6 +634,31 @@ static bool try_launch_encode(int block, int v, const EncArgs& a, dim3 grid, hip
 bool DQ_CAT(launch_encode_dim, DQ_DIM)(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
     DQ_CONFIGS(DQ_ENC_CASE)
     return false;
+}
+
+template <int D, int BB, int VV>
+static int try_encode_occupancy(int block, int v) {
+    if constexpr (D == DQ_DIM) {
+        if (block == BB && v == VV) {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_encode<D, BB, VV>),
+                                                             kThreads, 0) != hipSuccess)
+                return 0;
+            return n;
+        }
+    }
+    return -1;
+}
+
+#define DQ_OCC_CASE(D, BB, VV)                                          \
+    {                                                                   \
+        const int n = try_encode_occupancy<D, BB, VV>(block, v);        \
+        if (n >= 0) return n;                                           \
+    }
+
+int DQ_CAT(encode_occupancy_dim, DQ_DIM)(int block, int v) {
+    DQ_CONFIGS(DQ_OCC_CASE)
+    return 0;
 }
 
 }  // namespace dq

@@ -38,6 +38,17 @@ bool launch_decode_dim1(int block, int v, const DecArgs& a, dim3 grid, hipStream
 bool launch_decode_dim2(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
 bool launch_decode_dim3(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
 
+// Workgroups of the encode kernel that fit on one compute unit at once (0 if
+// not built or unknown); one workgroup holds one wave per SIMD.
+int encode_occupancy_dim1(int block, int v);
+int encode_occupancy_dim2(int block, int v);
+int encode_occupancy_dim3(int block, int v);
+inline int encode_occupancy(int dim, int block, int v) {
+    return dim == 1 ? encode_occupancy_dim1(block, v)
+         : dim == 2 ? encode_occupancy_dim2(block, v)
+         : dim == 3 ? encode_occupancy_dim3(block, v) : 0;
+}
+
 inline bool launch_encode(int dim, int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
     return dim == 1 ? launch_encode_dim1(block, v, a, grid, stream)
          : dim == 2 ? launch_encode_dim2(block, v, a, grid, stream)
