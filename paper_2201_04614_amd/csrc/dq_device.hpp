@@ -178,9 +178,15 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
 
 __device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
 
-// value of lane-1 (lane 0 receives 0): DPP wave_shr:1
+// value of lane-1 (lane 0 receives 0): DPP wave_shr:1. The empty asm keeps
+// the shifted value in a register of its own: folded into a subtraction
+// `x - shifted`, this compiler emits v_subrev_u32_dpp, which on gfx950
+// returned shifted - x (checked on the device; v_sub/v_add with DPP and a
+// DPP move were correct).
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+    uint32_t s = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, true);
+    __asm__("" : "+v"(s));
+    return s;
 }
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {

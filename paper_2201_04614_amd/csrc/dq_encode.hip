@@ -106,18 +106,24 @@ __device__ __forceinline__ void stage_row_outliers(const EncArgs& a, uint32_t& r
 template <int V, int NR>
 __device__ __forceinline__ void prequant_rows(const float (&xv)[NR][V], double r, double twoeb, double eb,
                                               uint32_t (&q)[NR][V], uint64_t& bad) {
-    bool slow = false;
+    // near-half test per value, as a ballot mask (false for NaN, so a
+    // non-finite x fails it); the range test on the running maximum of |x r|
+    // once for the batch
+    uint64_t near = 0;
+    double vmax = 0.0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             const double v = (double)xv[i][j] * r;
             const double k = __builtin_rint(v);
-            slow = slow || !(__builtin_fabs(v - k) <= kNearHalf && __builtin_fabs(v) <= kFastMax);
+            near |= ballot(!(__builtin_fabs(v - k) <= kNearHalf));
+            vmax = __builtin_fmax(vmax, __builtin_fabs(v));
             q[i][j] = (uint32_t)(int32_t)k;
         }
     }
-    if (__builtin_expect(ballot(slow) != 0, 0)) {
+    const bool slow = near != 0 || !(vmax <= kFastMax);
+    if (__builtin_expect(ballot(slow) != 0, 0)) {  // slow is wave-uniform except for vmax
         bool out = false;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -139,15 +145,15 @@ __device__ __forceinline__ void prequant_rows(const float (&xv)[NR][V], double r
 template <int DIM, int B, int V>
 __device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
                                         const float (&xv)[V], uint64_t row, uint32_t x0, bool xin, bool leader,
+                                        bool last,
                                         uint64_t gmask, uint32_t blk, double r, double twoeb, double eb,
                                         uint64_t& bad) {
     const uint32_t R = (uint32_t)a.R;
     uint32_t q[1][V];
     const float(&x1)[1][V] = reinterpret_cast<const float(&)[1][V]>(xv);
     prequant_rows<V, 1>(x1, r, twoeb, eb, q, bad);
-    const uint32_t left = wave_shr1(q[0][V - 1]);
     uint32_t u[V];
-    u[0] = q[0][0] - (leader ? 0u : left) + R;
+    u[0] = q[0][0] - wave_shr1(last ? 0u : q[0][V - 1]) + R;
 #pragma unroll
     for (int j = 1; j < V; ++j) u[j] = q[0][j] - q[0][j - 1] + R;
     uint32_t code[V];
@@ -180,7 +186,7 @@ __device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& s
 template <int DIM, int B, int V, int NR, bool FULL>
 __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
                                           const float (&xv)[NR][V], int zl, int yb, uint32_t z, uint32_t y0,
-                                          uint32_t x0, bool xin, bool leader, uint64_t gmask, uint32_t blk,
+                                          uint32_t x0, bool xin, bool leader, bool last, uint64_t gmask, uint32_t blk,
                                           double r, double twoeb, double eb, uint64_t& bad,
                                           Rsrc crs = Rsrc(), uint32_t csoff = 0) {
     const uint32_t R = (uint32_t)a.R;
@@ -194,9 +200,10 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         const int yl = yb + i;
-        const uint32_t left = wave_shr1(q[i][V - 1]);
+        // the left neighbour; a block's first lane receives 0 (the zero halo
+        // of the x difference) because the last lane of every block sends 0
         uint32_t d[V];
-        d[0] = q[i][0] - (leader ? 0u : left);
+        d[0] = q[i][0] - wave_shr1(last ? 0u : q[i][V - 1]);
 #pragma unroll
         for (int j = 1; j < V; ++j) d[j] = q[i][j] - q[i][j - 1];
 #pragma unroll
@@ -217,12 +224,19 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
         for (int j = 0; j < V; ++j) u[i][j] = d[j] + R;
     }
     const bool orow0 = (zl == 0) && (yb == 0);  // this batch starts with the block's first row
-    // phase 3: codes (the origin's code is rewritten at the end of the block)
+    // phase 3: codes (the origin's code is rewritten at the end of the block);
+    // code 0 marks an outlier, so the smallest code of the batch tells
+    // whether the outlier path is needed
+    uint32_t cmin = 0xffffffffu;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         uint32_t code[V];
 #pragma unroll
-        for (int j = 0; j < V; ++j) code[j] = is_inlier(u[i][j], R) ? u[i][j] : 0u;
+        for (int j = 0; j < V; ++j) {
+            code[j] = is_inlier(u[i][j], R) ? u[i][j] : 0u;
+            const bool skip = (!FULL && (!xin || y0 + i >= ny)) || (i == 0 && j == 0 && orow0 && leader);
+            cmin = min(cmin, skip ? 1u : code[j]);
+        }
         if (i == 0 && orow0 && leader) {
             st.qo = q[0][0];
 #pragma unroll
@@ -250,15 +264,7 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
         }
     }
     // phase 4: outliers, rare
-    bool anyout = false;
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-            anyout = anyout || ((FULL || y0 + i < ny) && !is_inlier(u[i][j], R) &&
-                                !(i == 0 && j == 0 && orow0 && leader));
-    }
-    if (ballot((FULL || xin) && anyout)) {
+    if (ballot(cmin == 0u)) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (!FULL && y0 + i >= ny) continue;  // uniform
@@ -385,6 +391,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     if constexpr (!C::WIDE) {
         const int gl = lane & (C::GPB - 1);
         const bool leader = gl == 0;
+        const bool last = gl == C::GPB - 1;
         const uint64_t gmask = (C::GPB == 64) ? ~0ull
                                               : (((1ull << C::GPB) - 1) << (lane & ~(C::GPB - 1)));
         if constexpr (DIM == 1) {
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
                     const bool xin = x0 < nx;
                     EncState<DIM, B, V> st;
                     st.init();
-                    enc_row<DIM, B, V>(a, st, w, xv[i], 0, x0, xin, leader, gmask, bx, r, twoeb, eb, bad);
+                    enc_row<DIM, B, V>(a, st, w, xv[i], 0, x0, xin, leader, last, gmask, bx, r, twoeb, eb, bad);
                     tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, 0, 0, bx, x0, gvalid, leader,
                                                            gpad, tile_total);
                 }
@@ -446,7 +453,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
                     constexpr int b = decltype(bI)::value;
                     constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
                     enc_batch<DIM, B, V, C::NBR, true>(a, st, w, buf[b % D], zl, yb, bz * B + zl, by * C::BY + yb,
-                                                       x0, true, leader, gmask, blk, r, twoeb, eb, bad, crs,
+                                                       x0, true, leader, last, gmask, blk, r, twoeb, eb, bad, crs,
                                                        ((uint32_t)zl * ny + yb) * nx * 2u);
                     if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
                 });
@@ -481,7 +488,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
                 };
                 auto compute_batch = [&](int zl, int yb, float (&buf)[C::NBR][V]) {
                     enc_batch<DIM, B, V, C::NBR, false>(a, st, w, buf, zl, yb, bz * B + zl, by * B + yb, x0, xin,
-                                                 leader, gmask, blk, r, twoeb, eb, bad);
+                                                 leader, last, gmask, blk, r, twoeb, eb, bad);
                 };
                 float bufA[C::NBR][V], bufB[C::NBR][V];
                 if constexpr (DIM == 3 && YB == 2) {
