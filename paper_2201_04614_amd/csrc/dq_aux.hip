@@ -59,12 +59,23 @@ void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream)
 
 // ------------------------------------------------------------------ value range (REL bound)
 
-__device__ __forceinline__ void minmax_acc(float e, uint32_t& kmin, uint32_t& kmax, bool& nf) {
-    const bool fin = __builtin_isfinite(e);
-    nf |= !fin;
-    const uint32_t k = fkey(e);
-    kmin = fin ? min(kmin, k) : kmin;
-    kmax = fin ? max(kmax, k) : kmax;
+// Running min / max of the values and a non-finite detector: fma(x, 0, acc)
+// turns NaN for an infinite or NaN x and stays NaN. On finite data the float
+// min / max are exact, so the bound equals the one over order-preserving
+// keys; with any non-finite value the call fails with ERANGE anyway.
+__device__ __forceinline__ void minmax_acc(float e, float& mn, float& mx, float& nfa) {
+    mn = __builtin_fminf(mn, e);
+    mx = __builtin_fmaxf(mx, e);
+    nfa = __builtin_fmaf(e, 0.0f, nfa);
+}
+
+__device__ __forceinline__ void minmax_acc4(const f32x4 v, float& mn, float& mx, float& nfa) {
+    mn = __builtin_fminf(mn, __builtin_fminf(__builtin_fminf(v.x, v.y), __builtin_fminf(v.z, v.w)));
+    mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fmaxf(v.x, v.y), __builtin_fmaxf(v.z, v.w)));
+    nfa = __builtin_fmaf(v.x, 0.0f, nfa);
+    nfa = __builtin_fmaf(v.y, 0.0f, nfa);
+    nfa = __builtin_fmaf(v.z, 0.0f, nfa);
+    nfa = __builtin_fmaf(v.w, 0.0f, nfa);
 }
 
 // Per-workgroup min / max keys and a non-finite flag (no atomics: every
@@ -74,13 +85,12 @@ __device__ __forceinline__ void minmax_acc(float e, uint32_t& kmin, uint32_t& km
 __global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restrict__ x, uint64_t N, uint4* parts,
                                                            int vec4, Scalars* sc, ResultDev* res) {
     constexpr int W = kMinmaxThreads / 64;
-    __shared__ uint32_t smin[W], smax[W], snf[W];
+    __shared__ float smin[W], smax[W], snf[W];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         init_scalars(sc, res);
         res->eb_abs = 0.0;
     }
-    uint32_t kmin = 0xffffffffu, kmax = 0u;
-    bool nf = false;
+    float mn = __builtin_inff(), mx = -__builtin_inff(), nfa = 0.0f;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t start = 0;
@@ -88,49 +98,36 @@ __global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restri
         const uint64_t n4 = N / 4;
         const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
         uint64_t i = tid;
-        for (; i + 3 * stride < n4; i += 4 * stride) {  // four 16-byte loads in flight
-            f32x4 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(x4 + i + u * stride);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                minmax_acc(v[u].x, kmin, kmax, nf);
-                minmax_acc(v[u].y, kmin, kmax, nf);
-                minmax_acc(v[u].z, kmin, kmax, nf);
-                minmax_acc(v[u].w, kmin, kmax, nf);
-            }
+        for (; i + stride < n4; i += 2 * stride) {  // two 16-byte loads in flight
+            const f32x4 v0 = __builtin_nontemporal_load(x4 + i);
+            const f32x4 v1 = __builtin_nontemporal_load(x4 + i + stride);
+            minmax_acc4(v0, mn, mx, nfa);
+            minmax_acc4(v1, mn, mx, nfa);
         }
-        for (; i < n4; i += stride) {
-            const f32x4 v = __builtin_nontemporal_load(x4 + i);
-            minmax_acc(v.x, kmin, kmax, nf);
-            minmax_acc(v.y, kmin, kmax, nf);
-            minmax_acc(v.z, kmin, kmax, nf);
-            minmax_acc(v.w, kmin, kmax, nf);
-        }
+        for (; i < n4; i += stride) minmax_acc4(__builtin_nontemporal_load(x4 + i), mn, mx, nfa);
         start = n4 * 4;
     }
-    for (uint64_t i = start + tid; i < N; i += stride) minmax_acc(x[i], kmin, kmax, nf);
+    for (uint64_t i = start + tid; i < N; i += stride) minmax_acc(x[i], mn, mx, nfa);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
-        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+        mn = __builtin_fminf(mn, __shfl_xor(mn, off));
+        mx = __builtin_fmaxf(mx, __shfl_xor(mx, off));
+        nfa += __shfl_xor(nfa, off);
     }
-    const bool anynf = ballot(nf) != 0;
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        smin[wave] = kmin;
-        smax[wave] = kmax;
-        snf[wave] = anynf ? 1u : 0u;
+        smin[wave] = mn;
+        smax[wave] = mx;
+        snf[wave] = nfa;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint4 pr = make_uint4(smin[0], smax[0], snf[0], 0u);
         for (int w = 1; w < W; ++w) {
-            pr.x = min(pr.x, smin[w]);
-            pr.y = max(pr.y, smax[w]);
-            pr.z |= snf[w];
+            mn = __builtin_fminf(mn, smin[w]);
+            mx = __builtin_fmaxf(mx, smax[w]);
+            nfa += snf[w];
         }
-        parts[blockIdx.x] = pr;
+        parts[blockIdx.x] = make_uint4(fkey(mn), fkey(mx), nfa != nfa ? 1u : 0u, 0u);
     }
 }
 
