@@ -58,44 +58,54 @@ def sinusoid_field(shape=(512, 512), n_waves=8, seed=1, noise=1e-3):
     return np.ascontiguousarray(f.astype(np.float32))
 
 
-def power_law_grf(shape=(256, 256, 256), slope=3.0, seed=2, workers=-1):
+def power_law_grf(shape=(256, 256, 256), slope=3.0, seed=2, workers=-1, dtype=np.float64):
     """Gaussian random field with power spectrum proportional to |k|^-slope.
 
     White N(0,1) noise is transformed with a real FFT, each mode is scaled by
     |k|^(-slope/2) using integer wavenumbers, the k = 0 mode is zeroed, and the
     inverse transform is normalised to zero mean and unit standard deviation.
+    dtype is the synthesis precision: fp64 (default) or fp32 for very large
+    fields (half the memory and time; the spectrum is scaled slab by slab).
     """
     shape = tuple(int(s) for s in shape)
     rng = np.random.default_rng(seed)
-    white = rng.standard_normal(shape)
+    if dtype == np.float32:
+        white = rng.standard_normal(shape, dtype=np.float32)
+    else:
+        white = rng.standard_normal(shape)
     spec = _rfftn(white, workers)
     del white
-    k2 = np.zeros(spec.shape, dtype=np.float64)
     nd = len(shape)
+    ks = []
     for ax, n in enumerate(shape):
-        if ax == nd - 1:
-            k = np.fft.rfftfreq(n) * n
-        else:
-            k = np.fft.fftfreq(n) * n
-        view = [1] * nd
-        view[ax] = k.size
-        k2 += (k * k).reshape(view)
-    with np.errstate(divide="ignore"):
-        amp = np.where(k2 > 0, k2 ** (-slope / 4.0), 0.0)
-    spec *= amp
-    del amp, k2
+        k = (np.fft.rfftfreq(n) if ax == nd - 1 else np.fft.fftfreq(n)) * n
+        ks.append(k * k)
+    rdt = np.float32 if dtype == np.float32 else np.float64
+    # |k|^2 of the trailing axes, then one slab of the leading axis at a time
+    tail = np.zeros(spec.shape[1:], dtype=np.float64)
+    for ax in range(1, nd):
+        view = [1] * (nd - 1)
+        view[ax - 1] = ks[ax].size
+        tail += ks[ax].reshape(view)
+    for i0 in range(spec.shape[0]):
+        k2 = tail + ks[0][i0]
+        with np.errstate(divide="ignore"):
+            amp = np.where(k2 > 0, k2 ** (-slope / 4.0), 0.0).astype(rdt)
+        spec[i0] *= amp
+    del tail
     f = _irfftn(spec, shape, workers)
     del spec
-    f -= f.mean()
-    sd = f.std()
+    f -= f.mean(dtype=np.float64)
+    sd = f.std(dtype=np.float64)
     if sd > 0:
-        f /= sd
+        f /= f.dtype.type(sd)
     return np.ascontiguousarray(f.astype(np.float32))
 
 
 def sharp_feature_field(shape=(512, 1024, 1024), seed=5, n_planes=25,
                         n_spheres=25, slope=3.0, workers=-1):
-    """k^-slope background plus planar step discontinuities and spherical shocks.
+    """k^-slope background (fp32 synthesis) plus planar step discontinuities
+    and spherical shocks.
 
     A planar step adds a * H(n . (p - c)) with a random unit normal n, a centre c
     uniform in the box and a = +-U(0.5, 2) (the background has unit standard
@@ -105,7 +115,7 @@ def sharp_feature_field(shape=(512, 1024, 1024), seed=5, n_planes=25,
     """
     shape = tuple(int(s) for s in shape)
     assert len(shape) == 3
-    f = power_law_grf(shape, slope=slope, seed=seed, workers=workers)
+    f = power_law_grf(shape, slope=slope, seed=seed, workers=workers, dtype=np.float32)
     rng = np.random.default_rng([seed, 0x5EED])
     nz, ny, nx = shape
     zc = np.arange(nz, dtype=np.float32)
@@ -142,6 +152,72 @@ def sharp_feature_field(shape=(512, 1024, 1024), seed=5, n_planes=25,
             inside = (dz2 + dyx2[None]) < np.float32(rho * rho)
             f[z0:z1, lo[1]:hi[1], lo[2]:hi[2]] += a * inside
     return f
+
+
+def sharp_feature_field_device(shape=(512, 1024, 1024), seed=5, n_planes=25, n_spheres=25, slope=3.0,
+                               device="cuda"):
+    """The recipe of sharp_feature_field synthesised on a GPU with torch (for
+    the 2 GiB configuration, where host synthesis takes minutes): the white
+    noise comes from a seeded torch generator on the device, the spectrum is
+    scaled by |k|^(-slope/2) with torch.fft, the result is normalised to zero
+    mean and unit standard deviation, and the same planar steps and spherical
+    shocks are added, their parameters drawn from the same numpy stream as the
+    host version. Returns an fp32 device tensor (C order). Deterministic for a
+    given seed, device and library build; the background differs from the
+    host version's (another random stream), the recipe is the same.
+    """
+    import torch
+
+    shape = tuple(int(s) for s in shape)
+    assert len(shape) == 3
+    nz, ny, nx = shape
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    white = torch.randn(shape, generator=gen, device=device, dtype=torch.float32)
+    spec = torch.fft.rfftn(white)
+    del white
+    kz = torch.fft.fftfreq(nz, d=1.0 / nz, device=device, dtype=torch.float64) ** 2
+    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device=device, dtype=torch.float64) ** 2
+    kx = torch.fft.rfftfreq(nx, d=1.0 / nx, device=device, dtype=torch.float64) ** 2
+    tail = (ky[:, None] + kx[None, :])
+    for i0 in range(nz):
+        k2 = tail + kz[i0]
+        amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (-slope / 4.0), torch.zeros_like(k2))
+        spec[i0] *= amp.to(torch.float32)
+    f = torch.fft.irfftn(spec, s=shape)
+    del spec
+    mean = f.mean(dtype=torch.float64)
+    sd = f.std(correction=0)
+    f -= mean.to(torch.float32)
+    if float(sd) > 0:
+        f /= sd
+    rng = np.random.default_rng([seed, 0x5EED])
+    zc = torch.arange(nz, device=device, dtype=torch.float32)
+    yc = torch.arange(ny, device=device, dtype=torch.float32)
+    xc = torch.arange(nx, device=device, dtype=torch.float32)
+    for _ in range(n_planes):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        c = rng.uniform(0.0, 1.0, 3) * np.array(shape, dtype=np.float64)
+        a = float(np.float32(rng.choice([-1.0, 1.0]) * rng.uniform(0.5, 2.0)))
+        t = ((float(n[0]) * (zc - float(c[0])))[:, None, None] + (float(n[1]) * (yc - float(c[1])))[None, :, None]
+             + (float(n[2]) * (xc - float(c[2])))[None, None, :])
+        f += a * (t > 0).to(torch.float32)
+        del t
+    L = max(shape)
+    for _ in range(n_spheres):
+        c = rng.uniform(0.0, 1.0, 3) * np.array(shape, dtype=np.float64)
+        rho = rng.uniform(0.05, 0.3) * L
+        a = float(np.float32(rng.choice([-1.0, 1.0]) * rng.uniform(0.5, 2.0)))
+        lo = [max(0, int(np.floor(c[i] - rho))) for i in range(3)]
+        hi = [min(shape[i], int(np.ceil(c[i] + rho)) + 1) for i in range(3)]
+        if any(h <= l for l, h in zip(lo, hi)):
+            continue
+        d2 = (((zc[lo[0]:hi[0]] - float(c[0])) ** 2)[:, None, None] + ((yc[lo[1]:hi[1]] - float(c[1])) ** 2)[None, :, None]
+              + ((xc[lo[2]:hi[2]] - float(c[2])) ** 2)[None, None, :])
+        f[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] += a * (d2 < float(np.float32(rho * rho))).to(torch.float32)
+        del d2
+    return f.contiguous()
 
 
 def field_range(x):

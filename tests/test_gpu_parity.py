@@ -51,6 +51,72 @@ def test_c2_grf_full_256(ref):
     assert c.n_out >= 32 ** 3
 
 
+def test_c5_sharp_features_full_size_sampled(ref):
+    """The 512 x 1024 x 1024 (2 GiB) sharp-feature workload, eb = 1e-4 * range, 8^3 blocks,
+    zero padding, at full size in the launch configuration of the other runs. The oracle
+    cannot run the whole field in seconds, so it runs on sampled block-aligned sub-boxes:
+    blocks are compressed independently, so a sub-box's codes, outliers (re-indexed, in
+    block-major order) and decoded values must equal the full run's. Over all cells: every
+    zero code has its outlier, and |x - x_hat| <= eb + half an ulp of x_hat."""
+    import torch
+
+    shape, B, R = (512, 1024, 1024), 8, 512
+    N = shape[0] * shape[1] * shape[2]
+    G.say("c5: synthesising the field on the device")
+    xd = F.sharp_feature_field_device(shape, seed=5)
+    x = xd.cpu().numpy()
+    eb = 1e-4 * F.field_range(x)
+    G.say(f"c5: eb={eb:.6g}, compressing")
+    codec = dq.Codec(shape, eb, "abs", B, "zero", R, out_cap=N // 16)
+    codec.compress_async(xd)
+    r = codec.result()
+    assert r.status == dq.DQ_OK, dq.strerror(r.status)
+    n_out = int(r.n_out)
+    xh_d = codec.decompress_async(r.eb_abs, n_out)
+    rd = codec.decompress_result()
+    assert rd.status == dq.DQ_OK, dq.strerror(rd.status)
+    torch.cuda.synchronize()
+    del xd
+    codes = codec.codes.cpu().numpy().view(np.uint16)
+    oi = codec.out_idx[:n_out].cpu().numpy().view(np.uint32)
+    ov = codec.out_val[:n_out].cpu().numpy()
+    xh = xh_d.cpu().numpy()
+    del xh_d
+    G.say(f"c5: n_out={n_out} ({100.0 * n_out / N:.4f} %), checking all cells")
+    assert int(np.count_nonzero(codes == 0)) == n_out
+    xf, hf = x.reshape(-1), xh.reshape(-1)
+    step = 1 << 24
+    for s0 in range(0, N, step):
+        a = xf[s0:s0 + step].astype(np.float64)
+        h = hf[s0:s0 + step]
+        half_ulp = 0.5 * np.spacing(np.abs(h)).astype(np.float64)
+        assert np.all(np.abs(a - h.astype(np.float64)) <= eb + half_ulp), s0
+    G.say("c5: sampled sub-boxes against the oracle")
+    gz, rest = np.divmod(oi.astype(np.int64), shape[1] * shape[2])
+    gy, gx = np.divmod(rest, shape[2])
+    rng = np.random.default_rng(55)
+    bdim = (4, 8, 16)  # sub-box extent in blocks: 32 x 64 x 128 cells
+    nb = [shape[a] // B for a in range(3)]
+    origins = [(0, 0, 0), tuple(nb[a] - bdim[a] for a in range(3))]
+    origins += [tuple(int(rng.integers(0, nb[a] - bdim[a] + 1)) for a in range(3)) for _ in range(10)]
+    for o in origins:
+        lo = [o[a] * B for a in range(3)]
+        hi = [lo[a] + bdim[a] * B for a in range(3)]
+        box = tuple(slice(lo[a], hi[a]) for a in range(3))
+        sub = np.ascontiguousarray(x[box])
+        p = ref.params(sub.shape, eb, "abs", B, "zero", R)
+        c = ref.compress(p, sub)
+        assert c.status == 0
+        assert np.array_equal(codes[box], c.codes), o
+        m = (gz >= lo[0]) & (gz < hi[0]) & (gy >= lo[1]) & (gy < hi[1]) & (gx >= lo[2]) & (gx < hi[2])
+        local = ((gz[m] - lo[0]) * sub.shape[1] + (gy[m] - lo[1])) * sub.shape[2] + (gx[m] - lo[2])
+        assert np.array_equal(local.astype(np.uint32), c.out_idx), o
+        assert np.array_equal(ov[m], c.out_val), o
+        st, xr = ref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads)
+        assert st == 0
+        assert np.array_equal(xh[box].view(np.uint32), xr.view(np.uint32)), o
+
+
 RAGGED = [
     ((1,), [1, 4]), ((3,), [1, 2, 4]), ((1000,), [1, 2, 8, 16, 256]), ((4099,), [4, 64, 128, 512]),
     ((12345,), [256, 1024, 4096]), ((1, 1), [1, 2]), ((37, 61), [1, 2, 4, 8, 16, 32]),
