@@ -1,21 +1,25 @@
 """Benchmark of the dual-quantisation hot path on one MI355X.
 
-Workload (one step): the 256^3 fp32 Gaussian random field with a k^-3 power
-spectrum (seed 2), relative error bound 1e-3, 8^3 blocks, radius 512, run
-through compress + decompress once per padding mode (zero, block mean, edge
-mean) - every stage of the path: value-range pass and bound resolution,
-prequantisation + Lorenzo + codes + outlier staging, outlier scan/scatter,
-outlier index, prefix-sum decode + dequantisation.
+Default workload (one step): the 256^3 fp32 Gaussian random field with a k^-3
+power spectrum (seed 2), relative error bound 1e-3, 8^3 blocks, radius 512,
+run through compress + decompress once per padding mode (zero, block mean,
+edge mean) - every stage of the path: value-range pass, prequantisation +
+Lorenzo + codes + outlier staging (bound resolved per wave), outlier
+placement, outlier index, prefix-sum decode + dequantisation.
+
+--workload c1 / c5 measure the 512^2 sinusoid field (abs eb 1e-4 * range,
+16^2 blocks, zero padding) and the 512 x 1024 x 1024 sharp-feature field
+(abs eb 1e-4 * range, 8^3 blocks, zero padding) the same way.
 
 Every call reads and writes its own buffers: inputs and outputs rotate over
-enough distinct sets that the working set (> 2 GiB) cannot stay in the 256 MB
+enough distinct sets that the working set (> 1 GiB) cannot stay in the 256 MB
 Infinity Cache, so the figure is HBM throughput. Inputs are resident in HBM
 before the timed region.
 
-Prints one JSON line: value = 3 * 4N bytes / step time (GB/s of fp32 input
-through compress + decompress), the roofline of the dominant kernel (timed
-with HIP events recorded around it inside the timed region), and the CPU
-oracle timed on a bounded sample.
+Prints one JSON line: value = (padding modes) * 4N bytes / step time (GB/s of
+fp32 input through compress + decompress), the roofline of the dominant
+kernel (timed with HIP events recorded around it), and the CPU oracle timed
+on a bounded sample.
 """
 
 import argparse
@@ -31,9 +35,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-PADS = ("zero", "block_mean", "edge_mean")
-SHAPE = (256, 256, 256)
-EB_REL, BLOCK, RADIUS, SEED = 1e-3, 8, 512, 2
+
+# name -> shape, bound (factor, mode: "rel" or "abs" times the field range),
+# block edge, padding modes, radius, rotating buffer sets, description
+WORKLOADS = {
+    "c2": dict(shape=(256, 256, 256), eb=1e-3, eb_mode="rel", block=8, radius=512, sets=4,
+               pads=("zero", "block_mean", "edge_mean"),
+               desc="256^3 fp32 k^-3 Gaussian random field (seed 2), rel eb 1e-3, 8^3 blocks, radius 512, "
+                    "padding zero/block_mean/edge_mean; step = compress+decompress per mode"),
+    "c1": dict(shape=(512, 512), eb=1e-4, eb_mode="abs", block=16, radius=512, sets=400, pads=("zero",),
+               desc="512^2 fp32 sum of 8 sinusoids + N(0,1e-3) noise (seed 1), abs eb 1e-4*range, 16^2 blocks, "
+                    "radius 512, zero padding; step = compress+decompress"),
+    "c5": dict(shape=(512, 1024, 1024), eb=1e-4, eb_mode="abs", block=8, radius=512, sets=1, pads=("zero",),
+               desc="512x1024x1024 fp32 k^-3 background + 25 planar steps + 25 spherical shocks (seed 5, "
+                    "device synthesis), abs eb 1e-4*range, 8^3 blocks, radius 512, zero padding; "
+                    "step = compress+decompress"),
+}
 
 
 def log(msg):
@@ -85,23 +102,33 @@ def copy_probe(reps=20):
     print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "reps": reps}), flush=True)
 
 
-def cpu_baseline(x, reps=1):
-    """The oracle, as it stands, on the same step (3 padding modes)."""
+def cpu_baseline(x, W, eb_abs):
+    """The oracle, as it stands, on a bounded sample of the same step: the
+    whole field up to 2^24 cells, else a block-aligned sub-box of 2^24 cells
+    (blocks are independent) with the bound of the full field."""
     from oracle import dqref
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    sample = "whole field"
+    if x.size > (1 << 24):
+        x = np.ascontiguousarray(x[: max(W["block"], (1 << 24) // (x.shape[1] * x.shape[2]))])
+        sample = f"sub-box {x.shape[0]}x{x.shape[1]}x{x.shape[2]} of the field"
     n = x.size
+    reps = max(1, int(2e6 // n))  # small fields: repeat to a measurable time
     t0 = time.perf_counter()
     for _ in range(reps):
-        for pad in PADS:
-            p = dqref.params(x.shape, EB_REL, "rel", BLOCK, pad, RADIUS)
+        for pad in W["pads"]:
+            if W["eb_mode"] == "rel" and sample == "whole field":
+                p = dqref.params(x.shape, W["eb"], "rel", W["block"], pad, W["radius"])
+            else:
+                p = dqref.params(x.shape, eb_abs, "abs", W["block"], pad, W["radius"])
             c = dqref.compress(p, x, out_cap=n // 16, nthreads=threads)
             st, _ = dqref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads, nthreads=threads)
             assert c.status == 0 and st == 0
     dt = time.perf_counter() - t0
-    return {"value": round(reps * len(PADS) * 4.0 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
+    npad = len(W["pads"])
+    return {"value": round(reps * npad * 4.0 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{reps} full step(s): 256^3 field, 3 padding modes, compress+decompress, "
-                      f"{dt:.1f} s wall"}
+            "sample": f"{reps} x ({sample}, {npad} padding mode(s), compress+decompress), {dt:.1f} s wall"}
 
 
 def main():
@@ -109,8 +136,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sets", type=int, default=4, help="rotating buffer sets per padding mode")
+    ap.add_argument("--sets", type=int, default=0, help="rotating buffer sets per padding mode (0 = workload's)")
     ap.add_argument("--vec", type=int, default=0, help="cells per lane hint (0 = automatic)")
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy used to scale the byte counters")
@@ -127,20 +155,33 @@ def main():
     from paper_2201_04614_amd import binding as dq
     from paper_2201_04614_amd import fields
 
+    W = WORKLOADS[args.workload]
+    SHAPE, BLOCK, RADIUS, PADS = W["shape"], W["block"], W["radius"], W["pads"]
+    sets = args.sets or W["sets"]
     dev = torch.device("cuda:0")
-    log("bench: generating 256^3 k^-3 field")
-    x = fields.power_law_grf(SHAPE, slope=3.0, seed=SEED)
+    log(f"bench: generating the {args.workload} field {SHAPE}")
+    if args.workload == "c2":
+        x = fields.power_law_grf(SHAPE, slope=3.0, seed=2)
+        xd = None
+    elif args.workload == "c1":
+        x = fields.sinusoid_field(SHAPE, seed=1)
+        xd = None
+    else:
+        xd = fields.sharp_feature_field_device(SHAPE, seed=5)
+        x = xd.cpu().numpy()
     n = x.size
-    xs = [[torch.from_numpy(x).to(dev) for _ in range(args.sets)] for _ in PADS]
-    codecs = [[dq.Codec(SHAPE, EB_REL, "rel", BLOCK, pad, RADIUS, out_cap=n // 16, device=dev, vec=args.vec)
-               for _ in range(args.sets)] for pad in PADS]
+    eb_arg = W["eb"] if W["eb_mode"] == "rel" else W["eb"] * fields.field_range(x)
+    xs = [[(xd if xd is not None else torch.from_numpy(x).to(dev)) for _ in range(sets)] for _ in PADS]
+    codecs = [[dq.Codec(SHAPE, eb_arg, W["eb_mode"], BLOCK, pad, RADIUS, out_cap=max(1024, n // 16), device=dev,
+                        vec=args.vec)
+               for _ in range(sets)] for pad in PADS]
     torch.cuda.synchronize()
 
     # warmup: also fixes each mode's outlier count and bound (identical every step)
     n_out, eb_abs = {}, {}
     for w in range(max(1, args.warmup)):
         for pi, pad in enumerate(PADS):
-            for s in range(args.sets):
+            for s in range(sets):
                 cd = codecs[pi][s]
                 cd.compress_async(xs[pi][s])
                 r = cd.result()
@@ -154,7 +195,7 @@ def main():
 
     def run_steps(hooks=None):
         for k in range(args.steps):
-            s = k % args.sets
+            s = k % sets
             for pi, pad in enumerate(PADS):
                 cd = codecs[pi][s]
                 he, hd = hooks[k][pi] if hooks else (None, None)
@@ -181,7 +222,7 @@ def main():
 
     # the timed results are the warmup's: same field, same outliers
     for pi, pad in enumerate(PADS):
-        for s in range(args.sets):
+        for s in range(sets):
             r = codecs[pi][s].result()
             assert r.status == dq.DQ_OK and int(r.n_out) == n_out[pad]
             assert codecs[pi][s].decompress_result().status == dq.DQ_OK
@@ -196,7 +237,7 @@ def main():
             hd.close()
 
     nb = dq.num_blocks(codecs[0][0].p)
-    pads_bytes = {"zero": 0, "block_mean": 4 * nb, "edge_mean": 12 * nb}
+    pads_bytes = {"zero": 0, "block_mean": 4 * nb, "edge_mean": 4 * len(SHAPE) * nb, "global_mean": 4}
     # algorithmic bytes per launch: encode reads x, writes codes, outliers
     # (index + value) and pads; decode reads the same stream and writes x_hat
     enc_bytes = {pad: 6.0 * n + 8.0 * n_out[pad] + pads_bytes[pad] for pad in PADS}
@@ -209,8 +250,9 @@ def main():
     achieved = kbytes / (kms * 1e-3) / 1e9
 
     value = len(PADS) * 4.0 * n / (ms_step * 1e-3) / 1e9
-    # bytes the whole step must move: value-range pass (4N) + encode + decode per mode
-    step_bytes = sum(4.0 * n + enc_bytes[p] + dec_bytes[p] for p in PADS)
+    # bytes the whole step must move: value-range pass (4N, relative bound) + encode + decode per mode
+    rel_pass = 4.0 * n if W["eb_mode"] == "rel" else 0.0
+    step_bytes = sum(rel_pass + enc_bytes[p] + dec_bytes[p] for p in PADS)
     out = {
         "metric": "dual-quant compress+decompress GB/s on 1 MI355X; % HBM peak; outlier %",
         "value": round(value, 2),
@@ -224,14 +266,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+i32",
         "data": "synthetic",
-        "config": {"workload": "256^3 fp32 k^-3 Gaussian random field (seed 2), rel eb 1e-3, "
-                               "8^3 blocks, radius 512, padding zero/block_mean/edge_mean; "
-                               "step = compress+decompress per mode",
-                   "shape": list(SHAPE), "block": BLOCK, "radius": RADIUS, "eb_rel": EB_REL,
-                   "buffer_sets": args.sets, "vec_hint": args.vec},
+        "config": {"workload": W["desc"], "shape": list(SHAPE), "block": BLOCK, "radius": RADIUS,
+                   "eb": W["eb"], "eb_mode": W["eb_mode"] + ("" if W["eb_mode"] == "rel" else " (x range)"),
+                   "buffer_sets": sets, "vec_hint": args.vec},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": stored_traffic() if kname == "encode" else None,
+                     "traffic": stored_traffic() if (kname == "encode" and args.workload == "c2") else None,
                      "avg_kernel_ms": round(kms, 5), "kernel_source_hash": kernel_source_hash()},
         "kernels_ms": {"encode": {p: round(v, 5) for p, v in enc_ms.items()},
                        "decode": {p: round(v, 5) for p, v in dec_ms.items()}},
@@ -243,7 +283,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(x)
+        out["cpu_baseline"] = cpu_baseline(x, W, eb_abs[PADS[0]])
     print(json.dumps(out), flush=True)
 
 

@@ -130,21 +130,30 @@ uint64_t max_tiles(const dq_params* p) {
     return m;
 }
 
+// Compress workspace: scalars, value-range partials, per-tile counts and
+// offsets, per-block outlier prefixes, then the outlier staging area: per-tile
+// regions of at most cap / 2 entries in all, and an overflow list of cap
+// entries (the overflow never exceeds the outlier count, so everything fits
+// whenever the outliers fit the caller's capacity).
 struct CompressLayout {
-    uint64_t sc, parts, tiles, info, stage, total;
+    uint64_t sc, parts, tiles, toff, info, region, ovf, cap, total;
 };
 
 CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     Geom g;
     base_geom(p, g);
     const uint64_t cap = out_cap < g.N ? out_cap : g.N;
+    const uint64_t mt = max_tiles(p);
     CompressLayout L;
+    L.cap = cap;
     L.sc = 0;
     L.parts = align_up(sizeof(Scalars));
     L.tiles = L.parts + align_up(sizeof(uint4) * kMinmaxParts);
-    L.info = L.tiles + align_up(4 * max_tiles(p));
-    L.stage = L.info + align_up(4ull * g.nblocks);
-    L.total = L.stage + align_up(16 * cap);
+    L.toff = L.tiles + align_up(4 * mt);
+    L.info = L.toff + align_up(4 * mt);
+    L.region = L.info + align_up(4ull * g.nblocks);
+    L.ovf = L.region + align_up(16 * (cap / 2));
+    L.total = L.ovf + align_up(16 * (cap > 0 ? cap : 1));
     return L;
 }
 
@@ -237,8 +246,13 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     char* w = static_cast<char*>(ws);
     Scalars* sc = reinterpret_cast<Scalars*>(w + L.sc);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(w + L.tiles);
+    uint32_t* toff = reinterpret_cast<uint32_t*>(w + L.toff);
     uint32_t* info = reinterpret_cast<uint32_t*>(w + L.info);
-    uint4* stage = reinterpret_cast<uint4*>(w + L.stage);
+    Staging stg;
+    stg.spt = (uint32_t)((cap / 2) / pl.g.n_tiles);
+    stg.region = reinterpret_cast<uint4*>(w + L.region);
+    stg.ovf = reinterpret_cast<uint4*>(w + L.ovf);
+    stg.ovf_cap = (uint32_t)cap;
     int32_t* status = &res->status;
 
     uint4* parts = reinterpret_cast<uint4*>(w + L.parts);
@@ -260,8 +274,7 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     ea.pads = pads;
     ea.block_info = info;
     ea.tile_count = tiles;
-    ea.stage = stage;
-    ea.stage_cap = (uint32_t)cap;
+    ea.stg = stg;
     ea.sc = sc;
     ea.status = status;
     ea.g = pl.g;
@@ -272,12 +285,10 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     if (!launch_encode(pl.dim, pl.B, pl.V, ea, grid, stream)) return DQ_ENOTSUP;
     if (hooks && hooks->ev_after) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_after), stream);
     if (pl.g.n_tiles <= kPlaceTiles) {
-        launch_place(stage, (uint32_t)cap, sc, res, out_cap, tiles, pl.g.n_tiles, info, pl.g, out_idx, out_val,
-                     stream);
+        launch_place(stg, sc, res, out_cap, tiles, pl.g.n_tiles, info, pl.g, out_idx, out_val, stream);
     } else {
-        launch_scan_tiles(tiles, pl.g.n_tiles, sc, status, res, out_cap, stream);
-        if (cap > 0)
-            launch_scatter(stage, (uint32_t)cap, sc, status, tiles, info, pl.g, out_idx, out_val, stream);
+        launch_scan_tiles(tiles, toff, pl.g.n_tiles, res, out_cap, stream);
+        if (cap > 0) launch_scatter(stg, sc, res, tiles, toff, pl.g.n_tiles, info, pl.g, out_idx, out_val, stream);
     }
     return check_launch();
 }

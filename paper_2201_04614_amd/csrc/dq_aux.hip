@@ -191,10 +191,10 @@ void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream) {
 
 // ------------------------------------------------------------------ scan of tile counts
 
-// Single workgroup, exclusive scan in place; writes n_out and the capacity
-// verdict.
-__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* cnt, uint32_t n, Scalars* sc, ResultDev* res,
-                                                     uint64_t out_cap) {
+// Single workgroup: exclusive scan of the tile counts into tile_off; writes
+// n_out and the capacity verdict (fields of more than kPlaceTiles tiles).
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* cnt, uint32_t* tile_off, uint32_t n,
+                                                     ResultDev* res, uint64_t out_cap) {
     __shared__ uint32_t wsum[16];
     __shared__ unsigned long long carry_s;
     constexpr int K = 8;  // items per thread per pass
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* cnt, uint32_t n, 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint64_t i = base + (uint64_t)tid * K + k;
-            if (i < n) cnt[i] = run;
+            if (i < n) tile_off[i] = run;
             run += v[k];
         }
         __syncthreads();
@@ -234,134 +234,161 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* cnt, uint32_t n, 
     }
     if (tid == 0) {
         const unsigned long long total = carry_s;
-        const int st = load_status(&res->status);
-        if (st == ST_OK) {
+        if (load_status(&res->status) == ST_OK) {
             res->n_out = total;
-            if (total > out_cap) res->status = ST_ECAPACITY;
+            if (total > out_cap) store_status(&res->status, ST_ECAPACITY);
         }
     }
 }
 
-void launch_scan_tiles(uint32_t* tile_count, uint32_t n_tiles, Scalars* sc, int32_t* status, void* res,
+void launch_scan_tiles(const uint32_t* tile_count, uint32_t* tile_off, uint32_t n_tiles, void* res,
                        uint64_t out_cap, hipStream_t stream) {
-    (void)status;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, stream, tile_count, n_tiles, sc, (ResultDev*)res,
-                       out_cap);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, stream, tile_count, tile_off, n_tiles,
+                       (ResultDev*)res, out_cap);
 }
 
 // ------------------------------------------------------------------ outlier scatter
 
-__global__ __launch_bounds__(256) void k_scatter(const uint4* __restrict__ stage, uint32_t cap,
-                                                 const Scalars* sc, const int32_t* status,
-                                                 const uint32_t* __restrict__ tile_offset,
-                                                 const uint32_t* __restrict__ block_info, Geom g,
-                                                 uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
-    if (load_status(status) != ST_OK) return;
-    const uint32_t n = min(sc->stage_count, cap);
-    // status OK means every outlier was staged (count <= cap); positions are
-    // checked against the count all the same
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint4 e = stage[i];
-        const uint32_t b = e.z;
-        const uint32_t bx = b % g.nbx;
-        const uint32_t rest = b / g.nbx;
-        const uint32_t by = rest % g.nby;
-        const uint32_t bz = rest / g.nby;
-        const uint32_t t = (bz * g.nby + by) * g.ntx + bx / g.bpt;
-        const uint32_t info = block_info[b];
-        uint32_t pos = tile_offset[t] + (info & ~kOriginFlag);
-        if (!(e.w & kOriginFlag)) pos += (info >> 31) + e.w;
-        if (pos < n) {
-            out_idx[pos] = e.x;
-            out_val[pos] = (int32_t)e.y;
+// Places every staged outlier once the tile offsets are known: each wave
+// walks the staging regions of its tiles, then the grid strides over the
+// overflow list. Nothing is written unless the list is complete (status OK).
+__device__ __forceinline__ void scatter_staged(const Staging& stg, uint32_t ovf_n, const uint32_t* tile_count,
+                                               const uint32_t* tile_off, uint32_t n_tiles,
+                                               const uint32_t* block_info, Geom g, uint32_t n,
+                                               uint32_t* out_idx, int32_t* out_val) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave_g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    if (stg.spt) {
+        for (uint32_t t = wave_g; t < n_tiles; t += waves) {
+            const uint32_t c = min(tile_count[t], stg.spt);
+            if (c == 0) continue;
+            const uint32_t off = tile_off[t];
+            const uint4* reg = stg.region + (uint64_t)t * stg.spt;
+            for (uint32_t i = (uint32_t)lane; i < c; i += 64) place_entry(reg[i], off, block_info, n, out_idx, out_val);
         }
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ovf_n; i += gridDim.x * blockDim.x) {
+        const uint4 e = stg.ovf[i];
+        place_entry(e, tile_off[block_tile(e.z, g)], block_info, n, out_idx, out_val);
     }
 }
 
-void launch_scatter(const uint4* stage, uint32_t stage_cap, const Scalars* sc, const int32_t* status,
-                    const uint32_t* tile_offset, const uint32_t* block_info, Geom g, uint32_t* out_idx,
-                    int32_t* out_val, hipStream_t stream) {
-    uint32_t blocks = (stage_cap + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, stream, stage, stage_cap, sc, status,
-                       tile_offset, block_info, g, out_idx, out_val);
+__global__ __launch_bounds__(256) void k_scatter(Staging stg, const Scalars* sc, const ResultDev* res,
+                                                 const uint32_t* __restrict__ tile_count,
+                                                 const uint32_t* __restrict__ tile_off, uint32_t n_tiles,
+                                                 const uint32_t* __restrict__ block_info, Geom g,
+                                                 uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
+    if (load_status(&res->status) != ST_OK) return;
+    const uint32_t n = (uint32_t)res->n_out;
+    scatter_staged(stg, min(sc->stage_count, stg.ovf_cap), tile_count, tile_off, n_tiles, block_info, g, n,
+                   out_idx, out_val);
+}
+
+void launch_scatter(const Staging& stg, const Scalars* sc, const void* res, const uint32_t* tile_count,
+                    const uint32_t* tile_off, uint32_t n_tiles, const uint32_t* block_info, Geom g,
+                    uint32_t* out_idx, int32_t* out_val, hipStream_t stream) {
+    const uint32_t blocks = 1024;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, stream, stg, sc, (const ResultDev*)res, tile_count,
+                       tile_off, n_tiles, block_info, g, out_idx, out_val);
 }
 
 // ------------------------------------------------------------------ fused scan + scatter
 
-// One kernel for fields of at most kPlaceTiles tiles: every workgroup that
-// has staged outliers to move computes the exclusive scan of the tile counts
-// in LDS itself (a few KB read from L2), then places its share of the staged
-// entries; workgroup 0 writes n_out and the capacity verdict. With no
-// outliers every workgroup but the first returns at once.
-__global__ __launch_bounds__(256) void k_place(const uint4* __restrict__ stage, uint32_t cap, const Scalars* sc,
-                                               ResultDev* res, uint64_t out_cap,
+// One kernel for fields of at most kPlaceTiles tiles. Workgroup w looks at
+// the tiles t = w (mod grid) and its slice of the overflow list; if it has
+// anything to place (and always for workgroup 0, which writes n_out and the
+// capacity verdict) it computes the exclusive scan of all tile counts in LDS
+// itself and places its share. With no outliers only workgroup 0 scans.
+//
+// The scan takes one round trip to L2: thread k loads the counts of tiles
+// 4k .. 4k+3 of every 1024-tile pass as one uint4 (the count array is padded
+// to 256 bytes, so reads up to the next multiple of 4 stay inside it; the
+// entries past n_tiles are masked), all passes are scanned at once and one
+// barrier publishes the per-wave sums.
+__global__ __launch_bounds__(256) void k_place(Staging stg, const Scalars* sc, ResultDev* res, uint64_t out_cap,
                                                const uint32_t* __restrict__ tile_count, uint32_t n_tiles,
                                                const uint32_t* __restrict__ block_info, Geom g,
                                                uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
-    __shared__ uint32_t pre[kPlaceTiles];
-    __shared__ uint32_t wsum[4];
-    const uint32_t staged = sc->stage_count;
-    const uint32_t n = min(staged, cap);
-    const bool lead = blockIdx.x == 0;
-    if (lead && staged == 0) {
-        if (threadIdx.x == 0 && load_status(&res->status) == ST_OK) res->n_out = 0;
-        return;
-    }
-    if (!lead && blockIdx.x * blockDim.x >= n) return;
-    // exclusive scan of the tile counts: thread k owns K consecutive tiles
+    constexpr int kPasses = kPlaceTiles / 1024;
+    __shared__ uint4 pre4[kPlaceTiles / 4];
+    __shared__ uint32_t wsum[kPasses][4];
+    const uint32_t* pre = reinterpret_cast<const uint32_t*>(pre4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t K = (n_tiles + 255) / 256;
-    uint32_t s = 0;
-    for (uint32_t k = 0; k < K; ++k) {
-        const uint32_t i = tid * K + k;
-        s += i < n_tiles ? tile_count[i] : 0u;
+    const uint32_t G = gridDim.x;
+    const bool lead = blockIdx.x == 0;
+    const uint32_t ovf_n = min(sc->stage_count, stg.ovf_cap);
+    if (!lead) {
+        bool mine = false;
+        for (uint32_t t = blockIdx.x + (uint32_t)tid * G; t < n_tiles; t += 256u * G) mine = mine || tile_count[t] != 0;
+        mine = __syncthreads_or(mine) || blockIdx.x * 256u < ovf_n;
+        if (!mine) return;
     }
-    const uint32_t incl = wave_scan_incl(s, lane);
-    if (lane == 63) wsum[wave] = incl;
+    const uint32_t n4 = (n_tiles + 3) / 4;
+    const uint4* cnt4 = reinterpret_cast<const uint4*>(tile_count);
+    uint4 v[kPasses];
+#pragma unroll
+    for (int j = 0; j < kPasses; ++j) v[j] = cnt4[min((uint32_t)tid + 256u * j, n4 - 1)];
+    uint32_t s[kPasses], incl[kPasses];
+#pragma unroll
+    for (int j = 0; j < kPasses; ++j) {
+        const uint32_t i = 4u * ((uint32_t)tid + 256u * j);
+        if (i >= n_tiles) v[j].x = 0u;
+        if (i + 1 >= n_tiles) v[j].y = 0u;
+        if (i + 2 >= n_tiles) v[j].z = 0u;
+        if (i + 3 >= n_tiles) v[j].w = 0u;
+        s[j] = v[j].x + v[j].y + v[j].z + v[j].w;
+        incl[j] = wave_scan_incl(s[j], lane);
+        if (lane == 63) wsum[j][wave] = incl[j];
+    }
     __syncthreads();
-    uint32_t run = incl - s;
-    for (int w = 0; w < wave; ++w) run += wsum[w];
-    for (uint32_t k = 0; k < K; ++k) {
-        const uint32_t i = tid * K + k;
-        if (i < n_tiles) {
-            pre[i] = run;
-            run += tile_count[i];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < kPasses; ++j) {
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t ws = wsum[j][w];
+            all += ws;
+            before += w < wave ? ws : 0u;
         }
+        const uint32_t run = carry + before + incl[j] - s[j];
+        const uint32_t i4 = (uint32_t)tid + 256u * j;
+        if (i4 < n4) {
+            const uint32_t r1 = run + v[j].x, r2 = r1 + v[j].y;
+            pre4[i4] = make_uint4(run, r1, r2, r2 + v[j].z);
+        }
+        carry += all;
     }
-    const uint64_t total = (uint64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    const uint64_t total = carry;  // the outlier count is below the cell count, below 2^32
     if (lead && tid == 0 && load_status(&res->status) == ST_OK) {
         res->n_out = total;
         if (total > out_cap) store_status(&res->status, ST_ECAPACITY);
     }
     __syncthreads();
-    if (total > out_cap || load_status(&res->status) != ST_OK) return;  // the list is incomplete anyway
-    for (uint32_t i = blockIdx.x * blockDim.x + tid; i < n; i += gridDim.x * blockDim.x) {
-        const uint4 e = stage[i];
-        const uint32_t b = e.z;
-        const uint32_t bx = b % g.nbx;
-        const uint32_t rest = b / g.nbx;
-        const uint32_t by = rest % g.nby;
-        const uint32_t bz = rest / g.nby;
-        const uint32_t t = (bz * g.nby + by) * g.ntx + bx / g.bpt;
-        const uint32_t info = block_info[b];
-        uint32_t pos = pre[t] + (info & ~kOriginFlag);
-        if (!(e.w & kOriginFlag)) pos += (info >> 31) + e.w;
-        if (pos < n) {
-            out_idx[pos] = e.x;
-            out_val[pos] = (int32_t)e.y;
+    if (total == 0 || total > out_cap || load_status(&res->status) != ST_OK) return;  // nothing, or incomplete
+    const uint32_t n = (uint32_t)total;
+    if (stg.spt) {
+        for (uint32_t t = blockIdx.x + (uint32_t)wave * G; t < n_tiles; t += 4u * G) {
+            const uint32_t c = min(tile_count[t], stg.spt);
+            if (c == 0) continue;
+            const uint4* reg = stg.region + (uint64_t)t * stg.spt;
+            for (uint32_t i = (uint32_t)lane; i < c; i += 64) place_entry(reg[i], pre[t], block_info, n, out_idx, out_val);
         }
+    }
+    for (uint32_t i = blockIdx.x * 256u + tid; i < ovf_n; i += G * 256u) {
+        const uint4 e = stg.ovf[i];
+        place_entry(e, pre[block_tile(e.z, g)], block_info, n, out_idx, out_val);
     }
 }
 
-void launch_place(const uint4* stage, uint32_t cap, const Scalars* sc, void* res, uint64_t out_cap,
-                  const uint32_t* tile_count, uint32_t n_tiles, const uint32_t* block_info, Geom g,
-                  uint32_t* out_idx, int32_t* out_val, hipStream_t stream) {
-    uint32_t blocks = (cap + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+void launch_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out_cap, const uint32_t* tile_count,
+                  uint32_t n_tiles, const uint32_t* block_info, Geom g, uint32_t* out_idx, int32_t* out_val,
+                  hipStream_t stream) {
+    uint32_t blocks = (n_tiles + 3) / 4;
+    if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, stream, stage, cap, sc, (ResultDev*)res, out_cap,
+    hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, stream, stg, sc, (ResultDev*)res, out_cap,
                        tile_count, n_tiles, block_info, g, out_idx, out_val);
 }
 

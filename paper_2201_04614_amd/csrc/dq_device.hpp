@@ -95,7 +95,7 @@ struct Scalars {
     double twoeb;          // 2 eb
     double r;              // fp64 reciprocal of 2 eb (first estimate only)
     unsigned long long sumq;   // int64 sum of q, two's complement (GLOBAL pad)
-    unsigned int stage_count;  // outliers staged so far
+    unsigned int stage_count;  // entries appended to the overflow staging list
     int gpad;                  // global pad value
 };
 
@@ -109,6 +109,19 @@ struct BoundArgs {
     double v;            // absolute bound, or the relative factor
 };
 
+// Staging of the outliers found by the encode pass, in the compress
+// workspace: every tile owns a region of spt slots (written without atomics);
+// what does not fit goes to an overflow list, appended with one atomic per
+// flush. Entries are (C-order index, delta, block id, rank among the block's
+// non-origin outliers | kOriginFlag for the origin) and say where they go,
+// so the order inside the staging area does not matter.
+struct Staging {
+    uint4* region;     // n_tiles * spt entries
+    uint32_t spt;      // slots per tile (may be 0)
+    uint4* ovf;        // overflow list
+    uint32_t ovf_cap;
+};
+
 struct EncArgs {
     BoundArgs bound;
     double* eb_out;        // dq_result.eb_abs (written for a relative bound)
@@ -117,8 +130,7 @@ struct EncArgs {
     int32_t* pads;
     uint32_t* block_info;  // per block: outliers of earlier blocks in the tile | origin flag
     uint32_t* tile_count;  // per tile: outliers in the tile
-    uint4* stage;          // (index, delta, block, rank | origin flag)
-    uint32_t stage_cap;
+    Staging stg;
     Scalars* sc;
     int32_t* status;       // dq_result.status
     Geom g;
@@ -559,21 +571,54 @@ __device__ __forceinline__ void load_codes_buf(Rsrc rs, uint32_t voff, uint32_t 
     }
 }
 
-// Write a wave's staged outliers (LDS) to the global staging list.
-__device__ __forceinline__ void flush_stage(uint4* sbuf, uint32_t n, uint4* stage, uint32_t cap,
-                                            unsigned int* counter, int lane) {
+// Move a wave's n LDS-staged outliers of tile t out of LDS: into the
+// tile's region while it has room (placed = slots already used), the rest to
+// the overflow list. Entries beyond the overflow capacity are dropped; that
+// only happens when the outliers exceed the caller's capacity (ECAPACITY).
+__device__ __forceinline__ void flush_stage(const uint4* sbuf, uint32_t n, const Staging& stg, uint32_t t,
+                                            uint32_t& placed, unsigned int* counter, int lane) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(counter, n);
-    base = readlane(base, 0);
-    for (uint32_t i = (uint32_t)lane; i < n; i += 64) {
-        if (base + i < cap) stage[base + i] = sbuf[i];
+    const uint32_t k = min(n, stg.spt - placed);
+    uint4* reg = stg.region + (uint64_t)t * stg.spt + placed;
+    for (uint32_t i = (uint32_t)lane; i < k; i += 64) reg[i] = sbuf[i];
+    placed += k;
+    const uint32_t rest = n - k;
+    if (rest) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(counter, rest);
+        base = readlane(base, 0);
+        for (uint32_t i = (uint32_t)lane; i < rest; i += 64) {
+            if ((uint64_t)base + i < stg.ovf_cap) stg.ovf[base + i] = sbuf[k + i];
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Final position of a staged outlier of tile t whose tile offset in the
+// list is off: the outliers of earlier blocks of the tile, then the block's
+// origin (if it is an outlier) and the other outliers in local row-major
+// order. Positions at or past n are not written.
+__device__ __forceinline__ void place_entry(const uint4 e, uint32_t off, const uint32_t* block_info, uint32_t n,
+                                            uint32_t* out_idx, int32_t* out_val) {
+    const uint32_t info = block_info[e.z];
+    uint32_t pos = off + (info & ~kOriginFlag);
+    if (!(e.w & kOriginFlag)) pos += (info >> 31) + e.w;
+    if (pos < n) {
+        out_idx[pos] = e.x;
+        out_val[pos] = (int32_t)e.y;
+    }
+}
+
+__device__ __forceinline__ uint32_t block_tile(uint32_t b, const Geom& g) {
+    const uint32_t bx = b % g.nbx;
+    const uint32_t rest = b / g.nbx;
+    const uint32_t by = rest % g.nby;
+    const uint32_t bz = rest / g.nby;
+    return (bz * g.nby + by) * g.ntx + bx / g.bpt;
 }
 
 }  // namespace dq

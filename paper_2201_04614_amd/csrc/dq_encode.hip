@@ -52,12 +52,14 @@ struct EncState {
 struct WaveCtx {
     uint4* sbuf;
     uint32_t scount;  // LDS staged entries (wave-uniform)
+    uint32_t placed;  // entries already in the tile's staging region
+    uint32_t t;       // tile
     int lane;
 };
 
 __device__ __forceinline__ void stage_push(const EncArgs& a, WaveCtx& w, uint32_t tot) {
     if (w.scount + tot > (uint32_t)kStageCap) {
-        flush_stage(w.sbuf, w.scount, a.stage, a.stage_cap, &a.sc->stage_count, w.lane);
+        flush_stage(w.sbuf, w.scount, a.stg, w.t, w.placed, &a.sc->stage_count, w.lane);
         w.scount = 0;
     }
 }
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
         if (lane == 0) a.tile_count[t] = 0;
         return;
     }
-    WaveCtx w{sbuf_all[wave], 0u, lane};
+    WaveCtx w{sbuf_all[wave], 0u, 0u, t, lane};
     const double r = bd.r, twoeb = bd.twoeb, eb = bd.eb;
     uint32_t gpad = 0;
     if (a.pad_mode == PAD_GLOBAL) {
@@ -614,7 +616,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
         }
     }
 
-    if (w.scount) flush_stage(w.sbuf, w.scount, a.stage, a.stage_cap, &a.sc->stage_count, lane);
+    if (w.scount) flush_stage(w.sbuf, w.scount, a.stg, t, w.placed, &a.sc->stage_count, lane);
     if (lane == 0) a.tile_count[t] = tile_total;
     if (bad && lane == 0) __hip_atomic_store(a.status, ST_ERANGE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
