@@ -14,7 +14,7 @@
  *  - prequantisation rounds the exact rational x / (2 eb) to the nearest
  *    integer, exact halves to even, and q must lie in [-(2^31-1), 2^31-1];
  *  - padding statistics are exact integer means of q, rounded half toward
- *    +infinity;
+ *    +infinity, or the minimum / maximum of q (block or global);
  *  - the edge padding of axis a is the mean of the block's own cells whose
  *    local coordinate along a is 0; a halo cell that lies in front of the
  *    block along several axes takes the rounded mean of those axes' values;
@@ -66,7 +66,7 @@ int dqref_validate(const dqref_params *p) {
     if (p->eb_mode != DQREF_EB_ABS && p->eb_mode != DQREF_EB_REL) return DQREF_EINVAL;
     if (p->eb_mode == DQREF_EB_ABS && !isfinite(1.0 / (2.0 * p->eb))) return DQREF_EINVAL;
     if (p->block < 1) return DQREF_EINVAL;
-    if (p->pad_mode < DQREF_PAD_ZERO || p->pad_mode > DQREF_PAD_GLOBAL_MEAN) return DQREF_EINVAL;
+    if (p->pad_mode < DQREF_PAD_ZERO || p->pad_mode > DQREF_PAD_GLOBAL_MAX) return DQREF_EINVAL;
     if (p->radius < 1 || p->radius > 32768) return DQREF_EINVAL;
     return DQREF_OK;
 }
@@ -101,8 +101,12 @@ int64_t dqref_pad_count(const dqref_params *p) {
     make_geom(p, &g);
     switch (p->pad_mode) {
     case DQREF_PAD_ZERO: return 0;
-    case DQREF_PAD_GLOBAL_MEAN: return 1;
-    case DQREF_PAD_BLOCK_MEAN: return g.nblocks;
+    case DQREF_PAD_GLOBAL_MEAN:
+    case DQREF_PAD_GLOBAL_MIN:
+    case DQREF_PAD_GLOBAL_MAX: return 1;
+    case DQREF_PAD_BLOCK_MEAN:
+    case DQREF_PAD_BLOCK_MIN:
+    case DQREF_PAD_BLOCK_MAX: return g.nblocks;
     default: return g.nblocks * g.d;
     }
 }
@@ -246,8 +250,9 @@ int dqref_prequantize(const dqref_params *p, const float *x, double eb_abs, int3
 
 /* ------------------------------------------------------------ padding */
 
-/* Padding values (Section IV-A: a statistic of the data; IV-B: one value
- * globally, one per block, or one per block and axis). */
+/* Padding values (Section IV-A: a statistic of the data - mean, minimum or
+ * maximum; IV-B: one value globally, one per block, or one per block and
+ * axis). */
 int dqref_pad_values(const dqref_params *p, const int32_t *q, int32_t *pads) {
     int st = dqref_validate(p);
     if (st != DQREF_OK) return st;
@@ -260,17 +265,29 @@ int dqref_pad_values(const dqref_params *p, const int32_t *q, int32_t *pads) {
         pads[0] = (int32_t)dqref_round_mean(S, g.N);
         return DQREF_OK;
     }
+    if (p->pad_mode == DQREF_PAD_GLOBAL_MIN || p->pad_mode == DQREF_PAD_GLOBAL_MAX) {
+        int32_t lo = q[0], hi = q[0];
+        for (int64_t i = 1; i < g.N; ++i) {
+            if (q[i] < lo) lo = q[i];
+            if (q[i] > hi) hi = q[i];
+        }
+        pads[0] = p->pad_mode == DQREF_PAD_GLOBAL_MIN ? lo : hi;
+        return DQREF_OK;
+    }
     for (int64_t b = 0; b < g.nblocks; ++b) {
         int64_t bc[3], ext[3], u[3], c[3];
         block_coords(&g, b, bc);
         block_extent(&g, bc, ext);
         int64_t cells = block_cells(&g, ext);
         int64_t S = 0, face_sum[3] = {0, 0, 0}, face_cnt[3] = {0, 0, 0};
+        int32_t lo = 0, hi = 0;
         for (int64_t k = 0; k < cells; ++k) {
             local_coords(&g, ext, k, u);
             for (int a = 0; a < g.d; ++a) c[a] = bc[a] * g.B + u[a];
             int32_t v = q[ravel(&g, c)];
             S += v;
+            if (k == 0 || v < lo) lo = v;
+            if (k == 0 || v > hi) hi = v;
             for (int a = 0; a < g.d; ++a) {
                 if (u[a] == 0) {
                     face_sum[a] += v;
@@ -280,6 +297,10 @@ int dqref_pad_values(const dqref_params *p, const int32_t *q, int32_t *pads) {
         }
         if (p->pad_mode == DQREF_PAD_BLOCK_MEAN) {
             pads[b] = (int32_t)dqref_round_mean(S, cells);
+        } else if (p->pad_mode == DQREF_PAD_BLOCK_MIN) {
+            pads[b] = lo;
+        } else if (p->pad_mode == DQREF_PAD_BLOCK_MAX) {
+            pads[b] = hi;
         } else {
             for (int a = 0; a < g.d; ++a)
                 pads[b * g.d + a] = (int32_t)dqref_round_mean(face_sum[a], face_cnt[a]);
@@ -294,8 +315,12 @@ static int32_t halo_value(const dqref_params *p, const geom *g, const int32_t *p
                           int64_t b, unsigned H) {
     switch (p->pad_mode) {
     case DQREF_PAD_ZERO: return 0;
-    case DQREF_PAD_GLOBAL_MEAN: return pads[0];
-    case DQREF_PAD_BLOCK_MEAN: return pads[b];
+    case DQREF_PAD_GLOBAL_MEAN:
+    case DQREF_PAD_GLOBAL_MIN:
+    case DQREF_PAD_GLOBAL_MAX: return pads[0];
+    case DQREF_PAD_BLOCK_MEAN:
+    case DQREF_PAD_BLOCK_MIN:
+    case DQREF_PAD_BLOCK_MAX: return pads[b];
     default: {
         int64_t S = 0;
         int m = popcount_u(H);

@@ -60,6 +60,12 @@ extern "C" {
 #define DQREF_PAD_BLOCK_MEAN 1
 #define DQREF_PAD_EDGE_MEAN 2
 #define DQREF_PAD_GLOBAL_MEAN 3
+/* Section IV-A also takes the minimum or the maximum of the data as the
+ * statistic, at block or global granularity (Section IV-B) */
+#define DQREF_PAD_BLOCK_MIN 4
+#define DQREF_PAD_BLOCK_MAX 5
+#define DQREF_PAD_GLOBAL_MIN 6
+#define DQREF_PAD_GLOBAL_MAX 7
 
 /* Field description. shape[0] is the slowest axis (C order); only the first
  * ndim entries are used. eb is the absolute bound (eb_mode ABS) or the
@@ -77,8 +83,9 @@ typedef struct {
 } dqref_params;
 
 int dqref_validate(const dqref_params *p);
-/* number of int32 pad values: 0 (zero), 1 (global), nBlocks (block),
- * nBlocks*ndim (edge); -1 on invalid parameters */
+/* number of int32 pad values: 0 (zero), 1 (global mean / min / max),
+ * nBlocks (block mean / min / max), nBlocks*ndim (edge); -1 on invalid
+ * parameters */
 int64_t dqref_pad_count(const dqref_params *p);
 int64_t dqref_num_blocks(const dqref_params *p);
 

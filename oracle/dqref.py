@@ -16,7 +16,8 @@ from . import build as _build
 
 OK, EINVAL, ERANGE, ECAPACITY, ECORRUPT = 0, -1, -2, -3, -6
 EB_MODES = {"abs": 0, "rel": 1}
-PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3}
+PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
+             "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7}
 
 
 class Params(C.Structure):

@@ -25,6 +25,7 @@ from fractions import Fraction
 import numpy as np
 
 ZERO, BLOCK_MEAN, EDGE_MEAN, GLOBAL_MEAN = 0, 1, 2, 3
+BLOCK_MIN, BLOCK_MAX, GLOBAL_MIN, GLOBAL_MAX = 4, 5, 6, 7
 
 
 def wrap32(a):
@@ -51,11 +52,15 @@ def pad_values(q, B, mode):
         return np.zeros(0, dtype=np.int64)
     if mode == GLOBAL_MEAN:
         return np.array([nearest_half_up(int(q.sum()), q.size)], dtype=np.int64)
+    if mode in (GLOBAL_MIN, GLOBAL_MAX):
+        return np.array([q.min() if mode == GLOBAL_MIN else q.max()], dtype=np.int64)
     out = []
     for sl in block_slices(q.shape, B):
         blk = q[sl]
         if mode == BLOCK_MEAN:
             out.append(nearest_half_up(int(blk.sum()), blk.size))
+        elif mode in (BLOCK_MIN, BLOCK_MAX):
+            out.append(int(blk.min() if mode == BLOCK_MIN else blk.max()))
         else:
             for a in range(d):
                 face = np.take(blk, 0, axis=a)
@@ -67,9 +72,9 @@ def halo_of(mode, pads, b, d, axes):
     """Padding value of a halo cell lying in front of the block along `axes`."""
     if mode == ZERO:
         return 0
-    if mode == GLOBAL_MEAN:
+    if mode in (GLOBAL_MEAN, GLOBAL_MIN, GLOBAL_MAX):
         return int(pads[0])
-    if mode == BLOCK_MEAN:
+    if mode in (BLOCK_MEAN, BLOCK_MIN, BLOCK_MAX):
         return int(pads[b])
     vals = [int(pads[b * d + a]) for a in axes]
     if len(vals) == 1:

@@ -19,8 +19,9 @@ import npref as NP
 from paper_2201_04614_amd import fields as F
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PADS = ["zero", "block_mean", "edge_mean", "global_mean"]
-PAD_ID = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3}
+PADS = ["zero", "block_mean", "edge_mean", "global_mean", "block_min", "block_max", "global_min", "global_max"]
+PAD_ID = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
+          "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7}
 
 
 def golden():
@@ -203,6 +204,12 @@ def _affine_expected_delta(shape, B, q0, slopes, pad):
         elif pad == "global_mean":
             peff = math.floor(Fraction(q0) + sum(Fraction(slopes[a] * (shape[a] - 1), 2)
                                                  for a in range(d)) + Fraction(1, 2))
+        elif pad in ("block_min", "block_max"):  # extreme corner of the block
+            pick = min if pad == "block_min" else max
+            peff = qo + sum(pick(0, slopes[a] * (ext[a] - 1)) for a in range(d))
+        elif pad in ("global_min", "global_max"):  # extreme corner of the field
+            pick = min if pad == "global_min" else max
+            peff = q0 + sum(pick(0, slopes[a] * (shape[a] - 1)) for a in range(d))
         else:  # edge: face a mean = centre of the face; inclusion-exclusion
             E = [math.floor(Fraction(qo) + sum(Fraction(slopes[b] * (ext[b] - 1), 2)
                                                 for b in range(d) if b != a) + Fraction(1, 2))
@@ -258,7 +265,7 @@ def test_constant_field(ref, shape, B, c0):
             else:
                 assert np.all(c.codes[origins] == 0)
                 assert c.n_out == origins.sum() and np.all(c.out_val == c0)
-        else:  # any mean padding equals the constant: nothing left to code
+        else:  # every statistic of a constant equals it: nothing left to code
             assert np.all(c.codes[origins] == R) and c.n_out == 0
 
 
@@ -371,6 +378,41 @@ def test_offset_field_padding_removes_border_outliers(ref):
     assert counts["block_mean"] < counts["zero"] and counts["edge_mean"] < counts["zero"]
 
 
+@pytest.mark.parametrize("shape,seed", [((300,), 1), ((37, 41), 2), ((9, 13, 11), 3)])
+def test_global_extreme_pad_is_prequantised_extreme(ref, shape, seed):
+    """Rounding to the nearest integer is monotone, so the minimum (maximum)
+    of q is the prequantised minimum (maximum) of x: the global min / max
+    pads need only the value range of the field."""
+    x = F.power_law_grf(shape, seed=seed) * np.float32(7.0) - np.float32(3.0)
+    for eb in (1e-2, 1e-3, 3.7e-5):
+        xe = np.array([x.min(), x.max()], dtype=np.float32)
+        pe = ref.params(xe.shape, eb, "abs", 4, "zero", 512)
+        st, qe = ref.prequantize(pe, xe, eb)
+        assert st == ref.OK
+        for pad, want in (("global_min", qe[0]), ("global_max", qe[1])):
+            p = ref.params(x.shape, eb, "abs", 4, pad, 512)
+            st, q = ref.prequantize(p, x, eb)
+            st, pads = ref.pad_values(p, q)
+            assert st == ref.OK and pads.shape == (1,) and pads[0] == want
+
+
+def test_extreme_pads_bound_the_origin_residual(ref):
+    """With block min (max) padding every origin residual is q_o - min >= 0
+    (q_o - max <= 0), and zero exactly where the origin holds the block's
+    extreme."""
+    x = F.power_law_grf((40, 36, 28), seed=9)
+    for pad, sign in (("block_min", 1), ("block_max", -1)):
+        p = ref.params(x.shape, 1e-3, "rel", 4, pad, 1 << 15)
+        c = ref.compress(p, x)
+        assert c.status == ref.OK and c.n_out == 0
+        origins = NP.origin_mask(x.shape, 4)
+        d0 = c.codes[origins].astype(np.int64) - (1 << 15)
+        assert np.all(sign * d0 >= 0)
+        st, q = ref.prequantize(p, x, c.eb_abs)
+        qo = q[origins].astype(np.int64)
+        assert np.array_equal(d0, qo - c.pads.astype(np.int64))
+
+
 # ------------------------------------------------------------ validation and errors
 
 def test_validation(ref):
@@ -378,7 +420,7 @@ def test_validation(ref):
     assert ref.validate(ref.params(**good)) == ref.OK
     bad = [dict(shape=(0, 10)), dict(shape=(2, 3, 4, 5)), dict(eb=0.0), dict(eb=-1.0),
            dict(eb=float("nan")), dict(eb=float("inf")), dict(eb=1e-320), dict(block=0),
-           dict(pad=7), dict(radius=0), dict(radius=32769), dict(eb_mode=5),
+           dict(pad=8), dict(pad=-1), dict(radius=0), dict(radius=32769), dict(eb_mode=5),
            dict(shape=(65536, 65536))]
     for b in bad:
         kw = dict(good)
