@@ -20,12 +20,12 @@
  *  - q is the nearest integer to the exact rational x / (2 eb), exact halves
  *    to even, so |x - 2 eb q| <= eb for every element; |q| <= 2^31 - 1;
  *  - arithmetic on q and delta wraps modulo 2^32 (the inverse is exact);
- *  - padding values are integer means of q, rounded to nearest with halves
- *    toward +infinity (Section IV-A: a statistic of the data; IV-B: one value
- *    per field, per block, or per block and axis). The EDGE value of axis a
- *    is the mean of the block's own cells whose local coordinate along a is
- *    0; a halo cell in front of the block along several axes takes the
- *    rounded mean of those axes' values;
+ *  - padding values are a statistic of q (Section IV-A): its integer mean,
+ *    rounded to nearest with halves toward +infinity, or its minimum or
+ *    maximum; taken per field, per block, or per block and axis (Section
+ *    IV-B). The EDGE value of axis a is the mean of the block's own cells
+ *    whose local coordinate along a is 0; a halo cell in front of the block
+ *    along several axes takes the rounded mean of those axes' values;
  *  - blocks are cubic (edge B along every axis of the field), aligned at the
  *    origin, truncated at the high end of each axis;
  *  - outliers are listed block by block (blocks in row-major order of the
@@ -74,7 +74,12 @@ typedef enum {
     DQ_PAD_ZERO = 0,        /* no side data */
     DQ_PAD_BLOCK_MEAN = 1,  /* one int32 per block */
     DQ_PAD_EDGE_MEAN = 2,   /* ndim int32 per block, axis-major inside a block */
-    DQ_PAD_GLOBAL_MEAN = 3  /* one int32 */
+    DQ_PAD_GLOBAL_MEAN = 3, /* one int32 */
+    DQ_PAD_BLOCK_MIN = 4,   /* one int32 per block: min of the block's q */
+    DQ_PAD_BLOCK_MAX = 5,   /* one int32 per block: max of the block's q */
+    DQ_PAD_GLOBAL_MIN = 6,  /* one int32: min of q over the field (also takes
+                               the value-range pass with an absolute bound) */
+    DQ_PAD_GLOBAL_MAX = 7   /* one int32: max of q over the field (idem) */
 } dq_pad_mode;
 
 /* Field and codec parameters.
@@ -126,8 +131,8 @@ dq_status dq_validate(const dq_params *p);
 /* Number of blocks of the field. */
 dq_status dq_num_blocks(const dq_params *p, uint64_t *n_blocks);
 
-/* Number of int32 padding values: 0 (ZERO), 1 (GLOBAL_MEAN), n_blocks
- * (BLOCK_MEAN), n_blocks * ndim (EDGE_MEAN). */
+/* Number of int32 padding values: 0 (ZERO), 1 (GLOBAL_MEAN / MIN / MAX),
+ * n_blocks (BLOCK_MEAN / MIN / MAX), n_blocks * ndim (EDGE_MEAN). */
 dq_status dq_pad_count(const dq_params *p, uint64_t *n_pads);
 
 /* Device workspace (bytes, 256-byte aligned start) needed by dq_compress

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libdq.so")
 
 DQ_OK, DQ_EINVAL, DQ_ERANGE, DQ_ECAPACITY, DQ_ENOTSUP, DQ_EDEVICE, DQ_ECORRUPT = 0, -1, -2, -3, -4, -5, -6
 EB_MODES = {"abs": 0, "rel": 1}
-PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3}
+PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
+             "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7}
 
 # every function include/dq.h declares
 EXPORTS = ["dq_validate", "dq_num_blocks", "dq_pad_count", "dq_compress_workspace",

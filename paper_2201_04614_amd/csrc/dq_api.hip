@@ -42,7 +42,7 @@ dq_status validate(const dq_params* p, bool check_eb) {
         if (p->eb_mode == DQ_EB_ABS && !isfinite(1.0 / (2.0 * p->eb))) return DQ_EINVAL;
     }
     if (p->block < 1) return DQ_EINVAL;
-    if (p->pad_mode < DQ_PAD_ZERO || p->pad_mode > DQ_PAD_GLOBAL_MEAN) return DQ_EINVAL;
+    if (p->pad_mode < DQ_PAD_ZERO || p->pad_mode > DQ_PAD_GLOBAL_MAX) return DQ_EINVAL;
     if (p->radius < 1 || p->radius > 32768) return DQ_EINVAL;
     if (p->vec != 0 && p->vec != 1 && p->vec != 2 && p->vec != 4) return DQ_EINVAL;
     // GPU kernel coverage
@@ -131,12 +131,12 @@ uint64_t max_tiles(const dq_params* p) {
 }
 
 // Compress workspace: scalars, value-range partials, per-tile counts and
-// offsets, per-block outlier prefixes, then the outlier staging area: per-tile
-// regions of at most cap / 2 entries in all, and an overflow list of cap
-// entries (the overflow never exceeds the outlier count, so everything fits
-// whenever the outliers fit the caller's capacity).
+// offsets, per-chunk count sums, per-block outlier prefixes, then the outlier
+// staging area: per-tile regions of at most cap / 2 entries in all, and an
+// overflow list of cap entries (the overflow never exceeds the outlier count,
+// so everything fits whenever the outliers fit the caller's capacity).
 struct CompressLayout {
-    uint64_t sc, parts, tiles, toff, info, region, ovf, cap, total;
+    uint64_t sc, parts, tiles, toff, csum, info, region, ovf, cap, total;
 };
 
 CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
@@ -150,7 +150,8 @@ CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     L.parts = align_up(sizeof(Scalars));
     L.tiles = L.parts + align_up(sizeof(uint4) * kMinmaxParts);
     L.toff = L.tiles + align_up(4 * mt);
-    L.info = L.toff + align_up(4 * mt);
+    L.csum = L.toff + align_up(4 * mt);
+    L.info = L.csum + align_up(4 * ((mt + kChunkTiles - 1) / kChunkTiles));
     L.region = L.info + align_up(4ull * g.nblocks);
     L.ovf = L.region + align_up(16 * (cap / 2));
     L.total = L.ovf + align_up(16 * (cap > 0 ? cap : 1));
@@ -199,8 +200,12 @@ dq_status dq_pad_count(const dq_params* p, uint64_t* n_pads) {
     if (!n_pads) return DQ_EINVAL;
     switch (p->pad_mode) {
     case DQ_PAD_ZERO: *n_pads = 0; break;
-    case DQ_PAD_GLOBAL_MEAN: *n_pads = 1; break;
-    case DQ_PAD_BLOCK_MEAN: *n_pads = nb; break;
+    case DQ_PAD_GLOBAL_MEAN:
+    case DQ_PAD_GLOBAL_MIN:
+    case DQ_PAD_GLOBAL_MAX: *n_pads = 1; break;
+    case DQ_PAD_BLOCK_MEAN:
+    case DQ_PAD_BLOCK_MIN:
+    case DQ_PAD_BLOCK_MAX: *n_pads = nb; break;
     default: *n_pads = nb * (uint64_t)p->ndim; break;
     }
     return DQ_OK;
@@ -257,9 +262,10 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
 
     uint4* parts = reinterpret_cast<uint4*>(w + L.parts);
     AuxArgs aa{x, sc, status, pl.g.N};
-    BoundArgs bound{parts, 0, p->eb};  // parts: read but unused for an absolute bound
-    if (p->eb_mode == DQ_EB_REL) {
-        bound.parts = parts;
+    // parts: read but unused without the value-range pass
+    BoundArgs bound{parts, 0, p->eb, p->eb_mode == DQ_EB_REL ? 1 : 0};
+    const bool extreme = p->pad_mode == DQ_PAD_GLOBAL_MIN || p->pad_mode == DQ_PAD_GLOBAL_MAX;
+    if (p->eb_mode == DQ_EB_REL || extreme) {
         bound.nparts = launch_minmax(aa, parts, res, stream);  // also initialises the call
     } else {
         launch_compress_init(sc, res, p->eb, stream);
@@ -287,8 +293,9 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     if (pl.g.n_tiles <= kPlaceTiles) {
         launch_place(stg, sc, res, out_cap, tiles, pl.g.n_tiles, info, pl.g, out_idx, out_val, stream);
     } else {
-        launch_scan_tiles(tiles, toff, pl.g.n_tiles, res, out_cap, stream);
-        if (cap > 0) launch_scatter(stg, sc, res, tiles, toff, pl.g.n_tiles, info, pl.g, out_idx, out_val, stream);
+        uint32_t* csum = reinterpret_cast<uint32_t*>(w + L.csum);
+        launch_chunked_place(stg, sc, res, out_cap, tiles, toff, csum, pl.g.n_tiles, info, pl.g, out_idx, out_val,
+                             stream);
     }
     return check_launch();
 }

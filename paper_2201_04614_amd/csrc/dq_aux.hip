@@ -4,7 +4,7 @@
 //              the consuming kernels resolve the bound per workgroup) ->
 //              [GLOBAL] sum of q -> encode -> scan of per-tile outlier counts and scatter
 //              of the staged outliers into block-major order (one fused
-//              kernel up to kPlaceTiles tiles, two kernels beyond)
+//              kernel up to kPlaceTiles tiles, three kernels beyond)
 //  decompress: [n_out > 0] per-block start of the outlier list (and
 //              validation of its order) -> decode (which also initialises the
 //              call's result)
@@ -189,108 +189,139 @@ void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream) {
     hipLaunchKernelGGL(k_sumq, dim3((uint32_t)blocks), dim3(256), 0, stream, a.x, a.N, a.sc, a.status, bound);
 }
 
-// ------------------------------------------------------------------ scan of tile counts
+// ------------------------------------------------------------------ large fields: chunked scan + scatter
 
-// Single workgroup: exclusive scan of the tile counts into tile_off; writes
-// n_out and the capacity verdict (fields of more than kPlaceTiles tiles).
-__global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* cnt, uint32_t* tile_off, uint32_t n,
-                                                     ResultDev* res, uint64_t out_cap) {
-    __shared__ uint32_t wsum[16];
-    __shared__ unsigned long long carry_s;
-    constexpr int K = 8;  // items per thread per pass
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) carry_s = 0;
+// Fields of more than kPlaceTiles tiles take three kernels. The tiles are cut
+// into chunks of kChunkTiles; k_chunk_sums writes each chunk's outlier total;
+// k_scatter_chunks (kChunkSplit workgroups per chunk, since outliers cluster
+// in a few chunks of fields with sharp features) turns them into the chunk's
+// carry, scans its tile counts into tile_off and places the entries of its
+// tiles' staging regions; k_scatter_overflow places the overflow list, whose
+// entries may belong to any tile.
+
+__device__ __forceinline__ uint32_t block_sum256(uint32_t v, uint32_t* red, int lane, int wave) {
+    const uint32_t incl = wave_scan_incl(v, lane);
+    if (lane == 63) red[wave] = incl;
     __syncthreads();
-    for (uint64_t base = 0; base < n; base += 1024ull * K) {
-        uint32_t v[K];
-        uint32_t s = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint64_t i = base + (uint64_t)tid * K + k;
-            v[k] = i < n ? cnt[i] : 0u;
-            s += v[k];
-        }
-        const uint32_t incl = wave_scan_incl(s, lane);
-        if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        uint32_t wbase = 0;
-        for (int w = 0; w < wave; ++w) wbase += wsum[w];
-        const unsigned long long carry = carry_s;
-        uint32_t run = (uint32_t)carry + wbase + incl - s;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint64_t i = base + (uint64_t)tid * K + k;
-            if (i < n) tile_off[i] = run;
-            run += v[k];
-        }
-        __syncthreads();
-        if (tid == 1023) {
-            uint32_t tot = 0;
-            for (int w = 0; w < 16; ++w) tot += wsum[w];
-            carry_s = carry + tot;
-        }
-        __syncthreads();
+    const uint32_t t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_sums(const uint32_t* __restrict__ cnt, uint32_t n_tiles,
+                                                    uint32_t* __restrict__ chunk_sum) {
+    __shared__ uint32_t red[4];
+    const int tid = threadIdx.x;
+    const uint32_t t = blockIdx.x * kChunkTiles + (uint32_t)tid;
+    const uint32_t v = t < n_tiles ? cnt[t] : 0u;
+    const uint32_t s = block_sum256(v, red, tid & 63, tid >> 6);
+    if (tid == 0) chunk_sum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* res, uint64_t out_cap,
+                                                        const uint32_t* __restrict__ cnt,
+                                                        uint32_t* __restrict__ tile_off,
+                                                        const uint32_t* __restrict__ chunk_sum, uint32_t n_tiles,
+                                                        uint32_t n_chunks, const uint32_t* __restrict__ block_info,
+                                                        uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
+    __shared__ uint32_t red[4], red2[4];
+    __shared__ uint32_t eoff[kChunkTiles + 1];  // exclusive prefix of the region entries per tile
+    __shared__ uint32_t toff_s[kChunkTiles];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t c = blockIdx.x / kChunkSplit;     // chunk
+    const uint32_t part = blockIdx.x % kChunkSplit;  // share of its entries
+    // carry of this chunk and the field's total
+    uint32_t before = 0, all = 0;
+    for (uint32_t i = (uint32_t)tid; i < n_chunks; i += 256u) {
+        const uint32_t v = chunk_sum[i];
+        all += v;
+        before += i < c ? v : 0u;
     }
-    if (tid == 0) {
-        const unsigned long long total = carry_s;
-        if (load_status(&res->status) == ST_OK) {
-            res->n_out = total;
-            if (total > out_cap) store_status(&res->status, ST_ECAPACITY);
+    const uint32_t carry = block_sum256(before, red, lane, wave);
+    const uint32_t total = block_sum256(all, red, lane, wave);
+    // tile offsets, and the prefix of the entries held in the regions
+    const uint32_t t = c * kChunkTiles + (uint32_t)tid;
+    const uint32_t k = t < n_tiles ? cnt[t] : 0u;
+    const uint32_t kr = min(k, stg.spt);
+    const uint32_t inc = wave_scan_incl(k, lane);
+    const uint32_t incr = wave_scan_incl(kr, lane);
+    if (lane == 63) {
+        red[wave] = inc;
+        red2[wave] = incr;
+    }
+    __syncthreads();
+    uint32_t wb = 0, wbr = 0;
+    for (int w = 0; w < wave; ++w) {
+        wb += red[w];
+        wbr += red2[w];
+    }
+    const uint32_t off = carry + wb + inc - k;
+    if (part == 0 && t < n_tiles) tile_off[t] = off;
+    toff_s[tid] = off;
+    eoff[tid + 1] = wbr + incr;
+    if (tid == 0) eoff[0] = 0u;
+    if (blockIdx.x == 0 && tid == 0 && load_status(&res->status) == ST_OK) {
+        res->n_out = total;
+        if (total > out_cap) store_status(&res->status, ST_ECAPACITY);
+    }
+    __syncthreads();
+    if (total == 0 || total > out_cap || load_status(&res->status) != ST_OK) return;  // nothing, or incomplete
+    const uint32_t E = eoff[kChunkTiles];
+    const uint64_t rbase = (uint64_t)c * kChunkTiles * stg.spt;
+    // flattened walk over the chunk's region entries, four per thread at a
+    // time; the kChunkSplit workgroups of a chunk take turns in strides of 1024
+    for (uint32_t k0 = part * 1024u; k0 < E; k0 += kChunkSplit * 1024u) {
+        uint4 e[4];
+        uint32_t o[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t q = k0 + (uint32_t)u * 256u + (uint32_t)tid;
+            ok[u] = q < E;
+            // last tile j with eoff[j] <= q
+            uint32_t lo = 0, hi = kChunkTiles;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (eoff[mid] <= q) lo = mid;
+                else hi = mid;
+            }
+            o[u] = toff_s[lo];
+            const uint64_t slot = rbase + (uint64_t)lo * stg.spt + (q - eoff[lo]);
+            e[u] = ok[u] ? stg.region[slot] : make_uint4(0u, 0u, 0u, 0u);
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u]) place_entry(e[u], o[u], block_info, total, out_idx, out_val);
     }
 }
 
-void launch_scan_tiles(const uint32_t* tile_count, uint32_t* tile_off, uint32_t n_tiles, void* res,
-                       uint64_t out_cap, hipStream_t stream) {
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, stream, tile_count, tile_off, n_tiles,
-                       (ResultDev*)res, out_cap);
-}
-
-// ------------------------------------------------------------------ outlier scatter
-
-// Places every staged outlier once the tile offsets are known: each wave
-// walks the staging regions of its tiles, then the grid strides over the
-// overflow list. Nothing is written unless the list is complete (status OK).
-__device__ __forceinline__ void scatter_staged(const Staging& stg, uint32_t ovf_n, const uint32_t* tile_count,
-                                               const uint32_t* tile_off, uint32_t n_tiles,
-                                               const uint32_t* block_info, Geom g, uint32_t n,
-                                               uint32_t* out_idx, int32_t* out_val) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave_g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    if (stg.spt) {
-        for (uint32_t t = wave_g; t < n_tiles; t += waves) {
-            const uint32_t c = min(tile_count[t], stg.spt);
-            if (c == 0) continue;
-            const uint32_t off = tile_off[t];
-            const uint4* reg = stg.region + (uint64_t)t * stg.spt;
-            for (uint32_t i = (uint32_t)lane; i < c; i += 64) place_entry(reg[i], off, block_info, n, out_idx, out_val);
-        }
-    }
+__global__ __launch_bounds__(256) void k_scatter_overflow(Staging stg, const Scalars* sc, const ResultDev* res,
+                                                          const uint32_t* __restrict__ tile_off,
+                                                          const uint32_t* __restrict__ block_info, Geom g,
+                                                          uint32_t* __restrict__ out_idx,
+                                                          int32_t* __restrict__ out_val) {
+    const uint32_t ovf_n = min(sc->stage_count, stg.ovf_cap);
+    if (blockIdx.x * blockDim.x >= ovf_n) return;
+    if (load_status(&res->status) != ST_OK) return;
+    const uint32_t n = (uint32_t)res->n_out;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ovf_n; i += gridDim.x * blockDim.x) {
         const uint4 e = stg.ovf[i];
         place_entry(e, tile_off[block_tile(e.z, g)], block_info, n, out_idx, out_val);
     }
 }
 
-__global__ __launch_bounds__(256) void k_scatter(Staging stg, const Scalars* sc, const ResultDev* res,
-                                                 const uint32_t* __restrict__ tile_count,
-                                                 const uint32_t* __restrict__ tile_off, uint32_t n_tiles,
-                                                 const uint32_t* __restrict__ block_info, Geom g,
-                                                 uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
-    if (load_status(&res->status) != ST_OK) return;
-    const uint32_t n = (uint32_t)res->n_out;
-    scatter_staged(stg, min(sc->stage_count, stg.ovf_cap), tile_count, tile_off, n_tiles, block_info, g, n,
-                   out_idx, out_val);
-}
-
-void launch_scatter(const Staging& stg, const Scalars* sc, const void* res, const uint32_t* tile_count,
-                    const uint32_t* tile_off, uint32_t n_tiles, const uint32_t* block_info, Geom g,
-                    uint32_t* out_idx, int32_t* out_val, hipStream_t stream) {
-    const uint32_t blocks = 1024;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, stream, stg, sc, (const ResultDev*)res, tile_count,
-                       tile_off, n_tiles, block_info, g, out_idx, out_val);
+void launch_chunked_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out_cap,
+                          const uint32_t* tile_count, uint32_t* tile_off, uint32_t* chunk_sum, uint32_t n_tiles,
+                          const uint32_t* block_info, Geom g, uint32_t* out_idx, int32_t* out_val,
+                          hipStream_t stream) {
+    const uint32_t n_chunks = (n_tiles + kChunkTiles - 1) / kChunkTiles;
+    hipLaunchKernelGGL(k_chunk_sums, dim3(n_chunks), dim3(256), 0, stream, tile_count, n_tiles, chunk_sum);
+    hipLaunchKernelGGL(k_scatter_chunks, dim3(n_chunks * kChunkSplit), dim3(256), 0, stream, stg, (ResultDev*)res,
+                       out_cap, tile_count, tile_off, (const uint32_t*)chunk_sum, n_tiles, n_chunks, block_info,
+                       out_idx, out_val);
+    if (stg.ovf_cap > 0)
+        hipLaunchKernelGGL(k_scatter_overflow, dim3(1024), dim3(256), 0, stream, stg, sc, (const ResultDev*)res,
+                           (const uint32_t*)tile_off, block_info, g, out_idx, out_val);
 }
 
 // ------------------------------------------------------------------ fused scan + scatter

@@ -20,18 +20,27 @@ template <int DIM>
 __device__ __forceinline__ uint32_t block_peff(const DecArgs& a, uint32_t blk) {
     const int pad = a.pad_mode;
     if (pad == PAD_ZERO) return 0u;
-    if (pad == PAD_GLOBAL) return (uint32_t)a.pads[0];
-    if (pad == PAD_BLOCK) return (uint32_t)a.pads[blk];
+    if (pad_global(pad)) return (uint32_t)a.pads[0];
+    if (pad_per_block(pad)) return (uint32_t)a.pads[blk];
     int32_t e[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) e[k] = a.pads[(uint64_t)blk * DIM + k];
     return edge_effective<DIM>(e);
 }
 
+// The first outliers of a wave's run of blocks, one per lane (idx, val of
+// entry base + lane for lane < cnt): zero codes take their outlier from here
+// with a lane shuffle instead of a load issued behind the prefetched codes.
+struct OutWin {
+    uint32_t idx = 0, val = 0;
+    uint32_t base = 0, cnt = 0;  // wave-uniform
+};
+
 template <int DIM, int B, int V>
 struct DecState {
     uint32_t rank;  // zero codes seen so far in this lane's block
     uint32_t os, oe;  // outlier run of the block
+    OutWin win;
     uint32_t peff;
     uint32_t pY[V];
     uint32_t pZ[DIM == 3 ? B : 1][V];
@@ -51,6 +60,19 @@ struct DecState {
 #pragma unroll
             for (int j = 0; j < V; ++j) pZ[k][j] = 0;
     }
+
+    // Load the window; every lane's block is valid and lane 63 holds the
+    // wave's last block (blocks in lane order), so the wave's outliers are
+    // entries os(lane 0) .. oe(lane 63).
+    __device__ __forceinline__ void prefetch(const DecArgs& a, int lane) {
+        win.base = uniform(os);
+        win.cnt = min(readlane(oe, 63) - win.base, 64u);
+        if (win.cnt) {
+            const uint32_t k = win.base + min((uint32_t)lane, win.cnt - 1u);
+            win.idx = a.out_idx[k];
+            win.val = (uint32_t)a.out_val[k];
+        }
+    }
 };
 
 // Replace zero codes of this row by their outliers: the k-th zero code of a
@@ -58,7 +80,7 @@ struct DecState {
 template <int V>
 __device__ __forceinline__ void fetch_outliers(const DecArgs& a, const uint32_t (&c)[V], uint32_t (&d)[V],
                                                uint32_t& rank, uint32_t os, uint32_t oe, uint64_t gmask,
-                                               uint64_t gbase, bool& corrupt) {
+                                               uint64_t gbase, bool& corrupt, const OutWin& w = OutWin{}) {
     bool anyzero = false;
 #pragma unroll
     for (int j = 0; j < V; ++j) anyzero = anyzero || c[j] == 0u;
@@ -74,11 +96,27 @@ __device__ __forceinline__ void fetch_outliers(const DecArgs& a, const uint32_t 
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            if (c[j] == 0u) {
-                const uint32_t k = os + rank + below + own;
-                ++own;
-                if (k < oe && a.out_idx[k] == (uint32_t)(gbase + j)) {
-                    d[j] = (uint32_t)a.out_val[k];
+            const bool z = c[j] == 0u;
+            const uint32_t k = os + rank + below + own;
+            own += z ? 1u : 0u;
+            const uint32_t kk = k - w.base;
+            uint32_t wi = 0, wv = 0;
+            if (w.cnt) {  // uniform: every lane takes part in the shuffle
+                const int src = (int)min(kk, 63u);
+                wi = (uint32_t)__shfl((int)w.idx, src);
+                wv = (uint32_t)__shfl((int)w.val, src);
+            }
+            if (z) {
+                bool have = false;
+                if (k < oe) {
+                    have = true;
+                    if (kk >= w.cnt) {
+                        wi = a.out_idx[k];
+                        wv = (uint32_t)a.out_val[k];
+                    }
+                }
+                if (have && wi == (uint32_t)(gbase + j)) {
+                    d[j] = wv;
                 } else {
                     corrupt = true;
                     d[j] = 0;
@@ -159,7 +197,7 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
 #pragma unroll
             for (int j = 0; j < V; ++j) cc[j] = (FULL || xin) ? c[i][j] : R;
             fetch_outliers<V>(a, cc, d[i], st.rank, st.os, st.oe, gmask, ((uint64_t)z * ny + y0 + i) * nx + x0,
-                              corrupt);
+                              corrupt, st.win);
         }
     }
 #pragma unroll
@@ -269,6 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
                     __builtin_amdgcn_sched_barrier(0);
                 };
                 static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
+                if (a.n_out) st.prefetch(a, lane);
                 static_for<0, NBT>([&](auto bI) {
                     constexpr int b = decltype(bI)::value;
                     constexpr int zl = b / YB, yb = (b % YB) * C::NBR;

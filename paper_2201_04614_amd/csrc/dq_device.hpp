@@ -26,6 +26,14 @@ constexpr int kTileTarget = 1024;         // minimum cells per tile (1-D, 2-D)
 
 constexpr int ST_OK = 0, ST_EINVAL = -1, ST_ERANGE = -2, ST_ECAPACITY = -3, ST_ECORRUPT = -6;
 constexpr int PAD_ZERO = 0, PAD_BLOCK = 1, PAD_EDGE = 2, PAD_GLOBAL = 3;
+constexpr int PAD_BLOCK_MIN = 4, PAD_BLOCK_MAX = 5, PAD_GLOBAL_MIN = 6, PAD_GLOBAL_MAX = 7;
+// one stored value per block / per field
+__host__ __device__ constexpr bool pad_per_block(int m) {
+    return m == PAD_BLOCK || m == PAD_BLOCK_MIN || m == PAD_BLOCK_MAX;
+}
+__host__ __device__ constexpr bool pad_global(int m) {
+    return m == PAD_GLOBAL || m == PAD_GLOBAL_MIN || m == PAD_GLOBAL_MAX;
+}
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -105,8 +113,9 @@ struct Scalars {
 // each workgroup of the consuming kernel reduces itself.
 struct BoundArgs {
     const uint4* parts;  // always a valid address of kBoundParts entries
-    int nparts;          // 0: v is the absolute bound
+    int nparts;          // value-range partials (0: no value-range pass)
     double v;            // absolute bound, or the relative factor
+    int rel;             // 1: eb = v * (max - min) over the partials
 };
 
 // Staging of the outliers found by the encode pass, in the compress
@@ -247,6 +256,20 @@ __device__ __forceinline__ uint32_t seg_scan_incl(uint32_t v, int lane) {
     return v;
 }
 
+// Minimum / maximum over aligned groups of G lanes.
+template <int G>
+__device__ __forceinline__ int32_t group_min32(int32_t v) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+template <int G>
+__device__ __forceinline__ int32_t group_max32(int32_t v) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
 // Sum over aligned groups of G lanes (every lane of a group gets the sum).
 template <int G>
 __device__ __forceinline__ long long group_sum64(long long v) {
@@ -365,7 +388,8 @@ __device__ __forceinline__ float funkey(uint32_t k) {
 
 struct Bound {
     double eb, twoeb, r;
-    int status;  // ST_OK, ST_ERANGE (non-finite input), ST_EINVAL (zero value range)
+    float mn, mx;  // value range of the field (with the value-range pass)
+    int status;    // ST_OK, ST_ERANGE (non-finite input), ST_EINVAL (zero value range)
 };
 
 // At most kBoundParts value-range partials (the value-range pass launches at
@@ -389,9 +413,9 @@ __device__ __forceinline__ void bound_fetch(const BoundArgs& b, uint4 (&pp)[kBou
 __device__ __forceinline__ Bound bound_finish(const BoundArgs& b, const uint4 (&pp)[kBoundPer], int lane) {
     Bound o;
     o.status = ST_OK;
-    if (b.nparts == 0) {
-        o.eb = b.v;
-    } else {
+    o.mn = o.mx = 0.0f;
+    o.eb = b.v;
+    if (b.nparts != 0) {
         uint32_t kmin = 0xffffffffu, kmax = 0u, nf = 0u;
 #pragma unroll
         for (int k = 0; k < kBoundPer; ++k) {
@@ -406,16 +430,17 @@ __device__ __forceinline__ Bound bound_finish(const BoundArgs& b, const uint4 (&
             kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
             nf |= (uint32_t)__shfl_xor((int)nf, off);
         }
-        const double mn = (double)funkey(kmin);
-        const double mx = (double)funkey(kmax);
-        o.eb = b.v * (mx - mn);
+        o.mn = __uint_as_float(uniform(__float_as_uint(funkey(kmin))));
+        o.mx = __uint_as_float(uniform(__float_as_uint(funkey(kmax))));
+        if (b.rel) o.eb = b.v * ((double)o.mx - (double)o.mn);
         if (nf) {
             o.status = ST_ERANGE;
-        } else if (!(o.eb > 0.0) || !__builtin_isfinite(o.eb) || !__builtin_isfinite(1.0 / (2.0 * o.eb))) {
+        } else if (b.rel &&
+                   (!(o.eb > 0.0) || !__builtin_isfinite(o.eb) || !__builtin_isfinite(1.0 / (2.0 * o.eb)))) {
             o.status = ST_EINVAL;
         }
     }
-    if (o.status != ST_OK) o.eb = 0.0;
+    if (o.status != ST_OK && b.rel) o.eb = 0.0;
     o.eb = uniform(o.eb);  // wave-uniform: keep the bound in scalar registers
     o.status = (int)uniform((uint32_t)o.status);
     o.twoeb = 2.0 * o.eb;

@@ -28,6 +28,7 @@ template <int DIM, int B, int V>
 struct EncState {
     uint32_t rank;  // non-origin outliers found so far in this lane's block
     long long s_all, s_fx, s_fy, s_fz;
+    int32_t vmin, vmax;  // block extremes of q (min / max padding)
     uint32_t qo;
     uint32_t dcode[V];
     uint32_t pY[V];
@@ -36,6 +37,8 @@ struct EncState {
     __device__ __forceinline__ void init() {
         rank = 0;
         s_all = s_fx = s_fy = s_fz = 0;
+        vmin = 0x7fffffff;
+        vmax = (int32_t)0x80000000;
         qo = 0;
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -170,6 +173,12 @@ __device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& s
 #pragma unroll
         for (int j = 0; j < V; ++j) rs += (int32_t)q[0][j];
         st.s_all += xin ? rs : 0ll;
+    } else if (a.pad_mode == PAD_BLOCK_MIN || a.pad_mode == PAD_BLOCK_MAX) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            st.vmin = xin ? min(st.vmin, (int32_t)q[0][j]) : st.vmin;
+            st.vmax = xin ? max(st.vmax, (int32_t)q[0][j]) : st.vmax;
+        }
     }
     if (leader) {
         st.qo = q[0][0];
@@ -249,7 +258,7 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
         else if (xin && y0 + i < ny)
             store_codes<V>(a.codes + ((uint64_t)z * ny + y0 + i) * nx + x0, code);
     }
-    // padding statistics (Section IV-A: mean of the data)
+    // padding statistics (Section IV-A: mean, minimum or maximum of the data)
     if (a.pad_mode == PAD_BLOCK || a.pad_mode == PAD_EDGE) {
         const bool pb = a.pad_mode == PAD_BLOCK, pe = !pb;
 #pragma unroll
@@ -263,6 +272,16 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
             st.s_fx += (pe && valid && leader) ? (long long)(int32_t)q[i][0] : 0ll;
             st.s_fy += (pe && yb + i == 0) ? rs : 0ll;
             if constexpr (DIM == 3) st.s_fz += (pe && zl == 0) ? rs : 0ll;
+        }
+    } else if (a.pad_mode == PAD_BLOCK_MIN || a.pad_mode == PAD_BLOCK_MAX) {  // minimum / maximum
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const bool valid = FULL || (xin && (y0 + i < ny));
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                st.vmin = valid ? min(st.vmin, (int32_t)q[i][j]) : st.vmin;
+                st.vmax = valid ? max(st.vmax, (int32_t)q[i][j]) : st.vmax;
+            }
         }
     }
     // phase 4: outliers, rare
@@ -288,8 +307,12 @@ __device__ __forceinline__ uint32_t enc_block_end(const EncArgs& a, EncState<DIM
     const uint32_t R = (uint32_t)a.R;
     const int pad = a.pad_mode;
     uint32_t peff = 0;
-    if (pad == PAD_GLOBAL) {
+    if (pad_global(pad)) {
         peff = gpad;
+    } else if (pad == PAD_BLOCK_MIN || pad == PAD_BLOCK_MAX) {
+        const int32_t P = pad == PAD_BLOCK_MIN ? group_min32<C::GPB>(st.vmin) : group_max32<C::GPB>(st.vmax);
+        peff = (uint32_t)P;
+        if (leader && gvalid) a.pads[blk] = P;
     } else if (pad != PAD_ZERO) {
         const long long ex = (long long)min((uint32_t)B, nx - min(nx, bx * B));
         const long long ey = DIM >= 2 ? (long long)min((uint32_t)B, ny - by * B) : 1;
@@ -379,6 +402,14 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     uint32_t gpad = 0;
     if (a.pad_mode == PAD_GLOBAL) {
         gpad = (uint32_t)round_mean((long long)a.sc->sumq, (long long)a.g.N);
+        if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
+    } else if (a.pad_mode == PAD_GLOBAL_MIN || a.pad_mode == PAD_GLOBAL_MAX) {
+        // rounding to the nearest integer is monotone, so the extreme of q
+        // is the pre-quantised extreme of x (an out-of-range one fails the
+        // call through its own element)
+        const float xe = a.pad_mode == PAD_GLOBAL_MIN ? bd.mn : bd.mx;
+        const double k = exact_round(xe, __builtin_rint((double)xe * r), twoeb, eb);
+        gpad = (uint32_t)(int32_t)(__builtin_fabs(k) <= kQMax ? k : 0.0);
         if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
     }
     const uint32_t tx = t % a.g.ntx;
@@ -533,6 +564,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
             if (bx >= a.g.nbx) break;
             uint32_t rank = 0, carry = 0, qo = 0;
             long long s_all = 0;
+            int32_t vmin = 0x7fffffff, vmax = (int32_t)0x80000000;
             uint32_t dcode[V];
 #pragma unroll
             for (int j = 0; j < V; ++j) dcode[j] = 0;
@@ -571,6 +603,12 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
                     if (a.pad_mode == PAD_BLOCK && xin) {
 #pragma unroll
                         for (int j = 0; j < V; ++j) s_all += (int32_t)q[i][j];
+                    } else if ((a.pad_mode == PAD_BLOCK_MIN || a.pad_mode == PAD_BLOCK_MAX) && xin) {
+#pragma unroll
+                        for (int j = 0; j < V; ++j) {
+                            vmin = min(vmin, (int32_t)q[i][j]);
+                            vmax = max(vmax, (int32_t)q[i][j]);
+                        }
                     }
                     if (origin_lane) {
                         qo = q[i][0];
@@ -583,8 +621,12 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
                 }
             }
             uint32_t peff = 0;
-            if (a.pad_mode == PAD_GLOBAL) {
+            if (pad_global(a.pad_mode)) {
                 peff = gpad;
+            } else if (a.pad_mode == PAD_BLOCK_MIN || a.pad_mode == PAD_BLOCK_MAX) {
+                const int32_t P = a.pad_mode == PAD_BLOCK_MIN ? group_min32<64>(vmin) : group_max32<64>(vmax);
+                peff = (uint32_t)P;
+                if (lane == 0) a.pads[bx] = P;
             } else if (a.pad_mode == PAD_BLOCK) {
                 const long long S = group_sum64<64>(s_all);
                 const long long ex = (long long)min((uint32_t)B, nx - bx * B);

@@ -85,11 +85,12 @@ constexpr int kMinmaxThreads = 1024;
 void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream);
 int launch_minmax(const AuxArgs& a, uint4* parts, void* res, hipStream_t stream);
 void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream);
-void launch_scan_tiles(const uint32_t* tile_count, uint32_t* tile_off, uint32_t n_tiles, void* res,
-                       uint64_t out_cap, hipStream_t stream);
-void launch_scatter(const Staging& stg, const Scalars* sc, const void* res, const uint32_t* tile_count,
-                    const uint32_t* tile_off, uint32_t n_tiles, const uint32_t* block_info, Geom g,
-                    uint32_t* out_idx, int32_t* out_val, hipStream_t stream);
+constexpr uint32_t kChunkTiles = 256;  // tiles per chunk of the large-field scan
+constexpr uint32_t kChunkSplit = 8;    // workgroups sharing a chunk's scatter
+void launch_chunked_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out_cap,
+                          const uint32_t* tile_count, uint32_t* tile_off, uint32_t* chunk_sum, uint32_t n_tiles,
+                          const uint32_t* block_info, Geom g, uint32_t* out_idx, int32_t* out_val,
+                          hipStream_t stream);
 constexpr uint32_t kPlaceTiles = 8192;  // tiles the fused scan + scatter holds in LDS
 void launch_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out_cap, const uint32_t* tile_count,
                   uint32_t n_tiles, const uint32_t* block_info, Geom g, uint32_t* out_idx, int32_t* out_val,

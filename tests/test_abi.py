@@ -46,7 +46,7 @@ def test_validate_host_only(L):
     ok = dq.make_params((10, 10), 1e-3, "abs", 4, "zero", 512)
     assert dq.validate(ok) == dq.DQ_OK
     bad = [dict(shape=(0, 10)), dict(eb=0.0), dict(eb=float("nan")), dict(eb=1e-320),
-           dict(block=0), dict(pad=7), dict(radius=0), dict(radius=32769), dict(eb_mode=3),
+           dict(block=0), dict(pad=8), dict(pad=-1), dict(radius=0), dict(radius=32769), dict(eb_mode=3),
            dict(shape=(65536, 65536))]
     base = dict(shape=(10, 10), eb=1e-3, eb_mode="abs", block=4, pad="zero", radius=512)
     for b in bad:
@@ -68,7 +68,8 @@ def test_counts_and_workspace(L):
     nb = 3 * 5 * 3
     assert dq.num_blocks(p) == nb
     assert dq.pad_count(p) == nb * 3
-    for pad, n in (("zero", 0), ("block_mean", nb), ("global_mean", 1)):
+    for pad, n in (("zero", 0), ("block_mean", nb), ("global_mean", 1), ("block_min", nb), ("block_max", nb),
+                   ("global_min", 1), ("global_max", 1)):
         assert dq.pad_count(dq.make_params((20, 33, 17), 1e-3, "rel", 8, pad)) == n
     w0 = dq.compress_workspace(p, 0)
     w1 = dq.compress_workspace(p, 1000)

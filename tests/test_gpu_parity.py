@@ -13,7 +13,7 @@ from paper_2201_04614_amd import fields as F
 
 pytestmark = pytest.mark.gpu
 
-PADS = ["zero", "block_mean", "edge_mean", "global_mean"]
+PADS = ["zero", "block_mean", "edge_mean", "global_mean", "block_min", "block_max", "global_min", "global_max"]
 
 
 def test_c1_sinusoid_512(ref):
@@ -195,7 +195,7 @@ def test_error_statuses(ref):
         y = x.copy()
         y[3, 7] = v
         for mode in ("abs", "rel"):
-            for pad in ("zero", "global_mean"):
+            for pad in ("zero", "global_mean", "global_min"):
                 G.parity(ref, y, 1e-3, mode, 8, pad, 512)
     y = x.copy()
     y[10, 10] = 1e7
@@ -212,6 +212,14 @@ def test_outlier_ordering_beyond_fused_tiles(ref, R):
     G.say(f"many tiles: n={n} R={R}")
     c = G.parity(ref, x, 1e-3, "abs", 16, "block_mean", R)
     assert c.n_out > 1000
+    # exact capacity: small staging regions, most entries take the overflow list
+    t = G.gpu_compress(x, 1e-3, "abs", 16, "block_mean", R, out_cap=c.n_out)
+    assert t["status"] == dq.DQ_OK and t["n_out"] == c.n_out
+    assert np.array_equal(t["out_idx"], c.out_idx) and np.array_equal(t["out_val"], c.out_val)
+    for cap in (c.n_out - 1, 0):
+        s = G.gpu_compress(x, 1e-3, "abs", 16, "block_mean", R, out_cap=cap)
+        assert s["status"] == dq.DQ_ECAPACITY and s["n_out"] == c.n_out
+        assert np.array_equal(s["codes"], c.codes)
 
 
 def test_capacity(ref):
