@@ -66,7 +66,7 @@ int dqref_validate(const dqref_params *p) {
     if (p->eb_mode != DQREF_EB_ABS && p->eb_mode != DQREF_EB_REL) return DQREF_EINVAL;
     if (p->eb_mode == DQREF_EB_ABS && !isfinite(1.0 / (2.0 * p->eb))) return DQREF_EINVAL;
     if (p->block < 1) return DQREF_EINVAL;
-    if (p->pad_mode < DQREF_PAD_ZERO || p->pad_mode > DQREF_PAD_GLOBAL_MAX) return DQREF_EINVAL;
+    if (p->pad_mode < DQREF_PAD_ZERO || p->pad_mode > DQREF_PAD_GIVEN) return DQREF_EINVAL;
     if (p->radius < 1 || p->radius > 32768) return DQREF_EINVAL;
     return DQREF_OK;
 }
@@ -106,7 +106,8 @@ int64_t dqref_pad_count(const dqref_params *p) {
     case DQREF_PAD_GLOBAL_MAX: return 1;
     case DQREF_PAD_BLOCK_MEAN:
     case DQREF_PAD_BLOCK_MIN:
-    case DQREF_PAD_BLOCK_MAX: return g.nblocks;
+    case DQREF_PAD_BLOCK_MAX:
+    case DQREF_PAD_GIVEN: return g.nblocks;
     default: return g.nblocks * g.d;
     }
 }
@@ -258,7 +259,7 @@ int dqref_pad_values(const dqref_params *p, const int32_t *q, int32_t *pads) {
     if (st != DQREF_OK) return st;
     geom g;
     make_geom(p, &g);
-    if (p->pad_mode == DQREF_PAD_ZERO) return DQREF_OK;
+    if (p->pad_mode == DQREF_PAD_ZERO || p->pad_mode == DQREF_PAD_GIVEN) return DQREF_OK;
     if (p->pad_mode == DQREF_PAD_GLOBAL_MEAN) {
         int64_t S = 0;
         for (int64_t i = 0; i < g.N; ++i) S += q[i];
@@ -320,7 +321,8 @@ static int32_t halo_value(const dqref_params *p, const geom *g, const int32_t *p
     case DQREF_PAD_GLOBAL_MAX: return pads[0];
     case DQREF_PAD_BLOCK_MEAN:
     case DQREF_PAD_BLOCK_MIN:
-    case DQREF_PAD_BLOCK_MAX: return pads[b];
+    case DQREF_PAD_BLOCK_MAX:
+    case DQREF_PAD_GIVEN: return pads[b];
     default: {
         int64_t S = 0;
         int m = popcount_u(H);

@@ -66,6 +66,9 @@ extern "C" {
 #define DQREF_PAD_BLOCK_MAX 5
 #define DQREF_PAD_GLOBAL_MIN 6
 #define DQREF_PAD_GLOBAL_MAX 7
+/* one value per block chosen by the caller (a per-block padding selector):
+ * pads is an input of compress, and the halo of block b is pads[b] */
+#define DQREF_PAD_GIVEN 8
 
 /* Field description. shape[0] is the slowest axis (C order); only the first
  * ndim entries are used. eb is the absolute bound (eb_mode ABS) or the
@@ -84,8 +87,8 @@ typedef struct {
 
 int dqref_validate(const dqref_params *p);
 /* number of int32 pad values: 0 (zero), 1 (global mean / min / max),
- * nBlocks (block mean / min / max), nBlocks*ndim (edge); -1 on invalid
- * parameters */
+ * nBlocks (block mean / min / max, given), nBlocks*ndim (edge); -1 on
+ * invalid parameters */
 int64_t dqref_pad_count(const dqref_params *p);
 int64_t dqref_num_blocks(const dqref_params *p);
 
@@ -96,7 +99,7 @@ int64_t dqref_round_mean(int64_t S, int64_t n);
 int dqref_resolve_eb(const dqref_params *p, const float *x, double *eb_abs);
 /* q[i] = nearest integer to the exact x[i] / (2 eb_abs), halves to even */
 int dqref_prequantize(const dqref_params *p, const float *x, double eb_abs, int32_t *q);
-/* pad values from q (length dqref_pad_count) */
+/* pad values from q (length dqref_pad_count); GIVEN leaves pads as they are */
 int dqref_pad_values(const dqref_params *p, const int32_t *q, int32_t *pads);
 /* Lorenzo residual of every element, natural (C-order) layout */
 int dqref_residuals(const dqref_params *p, const int32_t *q, const int32_t *pads,

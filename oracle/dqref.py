@@ -17,7 +17,7 @@ from . import build as _build
 OK, EINVAL, ERANGE, ECAPACITY, ECORRUPT = 0, -1, -2, -3, -6
 EB_MODES = {"abs": 0, "rel": 1}
 PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
-             "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7}
+             "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7, "given": 8}
 
 
 class Params(C.Structure):
@@ -154,7 +154,8 @@ class Compressed:
     eb_abs: float
 
 
-def compress(p, x, out_cap=None, nthreads=1):
+def compress(p, x, out_cap=None, nthreads=1, pads=None):
+    """pads: the per-block values of the "given" padding mode (an input)."""
     x = _f32(x)
     n = x.size
     if out_cap is None:
@@ -162,7 +163,12 @@ def compress(p, x, out_cap=None, nthreads=1):
     codes = np.zeros(x.shape, dtype=np.uint16)
     idx = np.zeros(max(int(out_cap), 1), dtype=np.uint32)
     val = np.zeros(max(int(out_cap), 1), dtype=np.int32)
-    pads = np.zeros(max(pad_count(p), 0), dtype=np.int32)
+    npad = max(pad_count(p), 0)
+    if pads is None:
+        pads = np.zeros(npad, dtype=np.int32)
+    else:
+        pads = np.array(pads, dtype=np.int32).reshape(-1)
+        assert pads.size == npad
     n_out = C.c_uint64(0)
     eb = C.c_double(0.0)
     st = lib().dqref_compress(C.byref(p), _ptr(x), _ptr(codes), _ptr(idx), _ptr(val),

@@ -26,6 +26,7 @@ import numpy as np
 
 ZERO, BLOCK_MEAN, EDGE_MEAN, GLOBAL_MEAN = 0, 1, 2, 3
 BLOCK_MIN, BLOCK_MAX, GLOBAL_MIN, GLOBAL_MAX = 4, 5, 6, 7
+GIVEN = 8  # per-block values supplied by the caller
 
 
 def wrap32(a):
@@ -74,7 +75,7 @@ def halo_of(mode, pads, b, d, axes):
         return 0
     if mode in (GLOBAL_MEAN, GLOBAL_MIN, GLOBAL_MAX):
         return int(pads[0])
-    if mode in (BLOCK_MEAN, BLOCK_MIN, BLOCK_MAX):
+    if mode in (BLOCK_MEAN, BLOCK_MIN, BLOCK_MAX, GIVEN):
         return int(pads[b])
     vals = [int(pads[b * d + a]) for a in axes]
     if len(vals) == 1:

@@ -396,6 +396,37 @@ def test_global_extreme_pad_is_prequantised_extreme(ref, shape, seed):
             assert st == ref.OK and pads.shape == (1,) and pads[0] == want
 
 
+@pytest.mark.parametrize("shape,B", [((101,), 8), ((23, 30), 4), ((9, 10, 11), 4)])
+def test_given_pads(ref, shape, B):
+    """Per-block values chosen by the caller: the halo of each block is its
+    value (checked against the halo-padded np.diff restatement); the block
+    means reproduce block-mean padding; the origin values themselves leave
+    every origin residual zero; random values round-trip."""
+    rng = np.random.default_rng(sum(shape) + B)
+    x = F.power_law_grf(shape, seed=7) * np.float32(50.0)
+    eb = 1e-2
+    pm = ref.params(shape, eb, "abs", B, "block_mean", 512)
+    cm = ref.compress(pm, x)
+    pg = ref.params(shape, eb, "abs", B, "given", 512)
+    cg = ref.compress(pg, x, pads=cm.pads)
+    assert cg.status == ref.OK and np.array_equal(cg.codes, cm.codes)
+    assert np.array_equal(cg.out_idx, cm.out_idx) and np.array_equal(cg.out_val, cm.out_val)
+    st, q = ref.prequantize(pg, x, eb)
+    origins = NP.origin_mask(shape, B)
+    qo = q[origins]  # block-major order equals the row-major order of the origins
+    co = ref.compress(pg, x, pads=qo)
+    assert np.all(co.codes[origins] == 512)
+    assert not np.any(np.isin(co.out_idx, np.flatnonzero(origins.ravel())))
+    rp = rng.integers(-3000, 3000, size=qo.size).astype(np.int32)
+    cr = ref.compress(pg, x, pads=rp)
+    assert cr.status == ref.OK and np.array_equal(cr.pads, rp)
+    st, d = ref.residuals(pg, q, rp)
+    assert np.array_equal(d.astype(np.int64), NP.residuals(q, B, NP.GIVEN, rp))
+    st, xh = ref.decompress(pg, cr.eb_abs, cr.codes, cr.out_idx, cr.out_val, cr.pads)
+    assert st == ref.OK
+    assert np.array_equal(xh, (q.astype(np.float64) * (2 * eb)).astype(np.float32))
+
+
 def test_extreme_pads_bound_the_origin_residual(ref):
     """With block min (max) padding every origin residual is q_o - min >= 0
     (q_o - max <= 0), and zero exactly where the origin holds the block's
@@ -420,7 +451,7 @@ def test_validation(ref):
     assert ref.validate(ref.params(**good)) == ref.OK
     bad = [dict(shape=(0, 10)), dict(shape=(2, 3, 4, 5)), dict(eb=0.0), dict(eb=-1.0),
            dict(eb=float("nan")), dict(eb=float("inf")), dict(eb=1e-320), dict(block=0),
-           dict(pad=8), dict(pad=-1), dict(radius=0), dict(radius=32769), dict(eb_mode=5),
+           dict(pad=9), dict(pad=-1), dict(radius=0), dict(radius=32769), dict(eb_mode=5),
            dict(shape=(65536, 65536))]
     for b in bad:
         kw = dict(good)
