@@ -79,7 +79,10 @@ typedef enum {
     DQ_PAD_BLOCK_MAX = 5,   /* one int32 per block: max of the block's q */
     DQ_PAD_GLOBAL_MIN = 6,  /* one int32: min of q over the field (also takes
                                the value-range pass with an absolute bound) */
-    DQ_PAD_GLOBAL_MAX = 7   /* one int32: max of q over the field (idem) */
+    DQ_PAD_GLOBAL_MAX = 7,  /* one int32: max of q over the field (idem) */
+    DQ_PAD_GIVEN = 8        /* one int32 per block chosen by the caller (a
+                               per-block padding selector): an INPUT of
+                               dq_compress, the halo value of its block */
 } dq_pad_mode;
 
 /* Field and codec parameters.
@@ -132,7 +135,7 @@ dq_status dq_validate(const dq_params *p);
 dq_status dq_num_blocks(const dq_params *p, uint64_t *n_blocks);
 
 /* Number of int32 padding values: 0 (ZERO), 1 (GLOBAL_MEAN / MIN / MAX),
- * n_blocks (BLOCK_MEAN / MIN / MAX), n_blocks * ndim (EDGE_MEAN). */
+ * n_blocks (BLOCK_MEAN / MIN / MAX, GIVEN), n_blocks * ndim (EDGE_MEAN). */
 dq_status dq_pad_count(const dq_params *p, uint64_t *n_pads);
 
 /* Device workspace (bytes, 256-byte aligned start) needed by dq_compress
@@ -142,8 +145,9 @@ dq_status dq_decompress_workspace(const dq_params *p, uint64_t *bytes);
 
 /* Compress x (N fp32, C order) into codes (N uint16, C order), the outlier
  * list out_idx/out_val (room for out_cap entries, block-major order) and pads
- * (dq_pad_count int32). out_idx/out_val may be NULL when out_cap == 0; pads
- * may be NULL when dq_pad_count is 0. res receives status, n_out, eb_abs.
+ * (dq_pad_count int32; read instead of written for DQ_PAD_GIVEN). out_idx/
+ * out_val may be NULL when out_cap == 0; pads may be NULL when dq_pad_count
+ * is 0. res receives status, n_out, eb_abs.
  * If n_out > out_cap the status is DQ_ECAPACITY, the codes are complete, the
  * outlier list is not, and n_out is exact: retry with out_cap >= n_out.
  * x, codes and ws must not overlap any other buffer. */

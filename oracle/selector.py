@@ -6,7 +6,7 @@ this module; the product path never does.
 The paper chooses padding values from statistics of the data (Section IV-A:
 mean, minimum, maximum; Section IV-B: per field, per block or per block and
 axis) and tunes the block size by searching the configurations (Section
-III-C autotuning). This module states, plainly and slowly, what the GPU
+III-E autotuning). This module states, plainly and slowly, what the GPU
 selector computes:
 
 * block statistics of the pre-quantised field q (integers, exact);
@@ -299,3 +299,21 @@ def init_params(seed=0):
         else:
             P[name] = np.zeros(shp)
     return pack(P)
+
+
+def bf16_round(a):
+    """fp32 values rounded to bfloat16 (nearest, ties to even), as fp32."""
+    a = np.asarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def forward_bf16(theta, X):
+    """Logits of the network with its parameters, inputs and hidden
+    activations rounded to bfloat16, the products summed exactly (fp64)."""
+    P = unpack(bf16_round(np.asarray(theta, dtype=np.float32)).astype(np.float64))
+    x = bf16_round(np.asarray(X, dtype=np.float32)).astype(np.float64)
+    h1 = bf16_round(np.maximum(x @ P["W1"].T + P["b1"], 0.0).astype(np.float32)).astype(np.float64)
+    h2 = bf16_round(np.maximum(h1 @ P["W2"].T + P["b2"], 0.0).astype(np.float32)).astype(np.float64)
+    return h2 @ P["W3"].T + P["b3"]

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdq.so")
 DQ_OK, DQ_EINVAL, DQ_ERANGE, DQ_ECAPACITY, DQ_ENOTSUP, DQ_EDEVICE, DQ_ECORRUPT = 0, -1, -2, -3, -4, -5, -6
 EB_MODES = {"abs": 0, "rel": 1}
 PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
-             "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7}
+             "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7, "given": 8}
 
 # every function include/dq.h declares
 EXPORTS = ["dq_validate", "dq_num_blocks", "dq_pad_count", "dq_compress_workspace",
@@ -246,7 +246,9 @@ class Codec:
         self.x_hat = torch.empty(self.shape, dtype=torch.float32, device=self.device)
 
     def compress_async(self, x, stream=None, hooks=None):
-        """Enqueue compression of x (contiguous fp32 CUDA tensor of this shape)."""
+        """Enqueue compression of x (contiguous fp32 CUDA tensor of this shape).
+        With the "given" padding mode, self.pads holds the per-block values
+        (an input) when this is called."""
         assert x.is_cuda and x.dtype == _torch().float32 and x.is_contiguous()
         assert tuple(x.shape) == self.shape
         st = lib().dq_compress(C.byref(self.p), _ptr(x), _ptr(self.codes), _ptr(self.out_idx),

@@ -42,7 +42,7 @@ dq_status validate(const dq_params* p, bool check_eb) {
         if (p->eb_mode == DQ_EB_ABS && !isfinite(1.0 / (2.0 * p->eb))) return DQ_EINVAL;
     }
     if (p->block < 1) return DQ_EINVAL;
-    if (p->pad_mode < DQ_PAD_ZERO || p->pad_mode > DQ_PAD_GLOBAL_MAX) return DQ_EINVAL;
+    if (p->pad_mode < DQ_PAD_ZERO || p->pad_mode > DQ_PAD_GIVEN) return DQ_EINVAL;
     if (p->radius < 1 || p->radius > 32768) return DQ_EINVAL;
     if (p->vec != 0 && p->vec != 1 && p->vec != 2 && p->vec != 4) return DQ_EINVAL;
     // GPU kernel coverage
@@ -205,7 +205,8 @@ dq_status dq_pad_count(const dq_params* p, uint64_t* n_pads) {
     case DQ_PAD_GLOBAL_MAX: *n_pads = 1; break;
     case DQ_PAD_BLOCK_MEAN:
     case DQ_PAD_BLOCK_MIN:
-    case DQ_PAD_BLOCK_MAX: *n_pads = nb; break;
+    case DQ_PAD_BLOCK_MAX:
+    case DQ_PAD_GIVEN: *n_pads = nb; break;
     default: *n_pads = nb * (uint64_t)p->ndim; break;
     }
     return DQ_OK;

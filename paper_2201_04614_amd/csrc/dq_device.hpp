@@ -27,9 +27,10 @@ constexpr int kTileTarget = 1024;         // minimum cells per tile (1-D, 2-D)
 constexpr int ST_OK = 0, ST_EINVAL = -1, ST_ERANGE = -2, ST_ECAPACITY = -3, ST_ECORRUPT = -6;
 constexpr int PAD_ZERO = 0, PAD_BLOCK = 1, PAD_EDGE = 2, PAD_GLOBAL = 3;
 constexpr int PAD_BLOCK_MIN = 4, PAD_BLOCK_MAX = 5, PAD_GLOBAL_MIN = 6, PAD_GLOBAL_MAX = 7;
+constexpr int PAD_GIVEN = 8;  // per-block values supplied by the caller (read by encode)
 // one stored value per block / per field
 __host__ __device__ constexpr bool pad_per_block(int m) {
-    return m == PAD_BLOCK || m == PAD_BLOCK_MIN || m == PAD_BLOCK_MAX;
+    return m == PAD_BLOCK || m == PAD_BLOCK_MIN || m == PAD_BLOCK_MAX || m == PAD_GIVEN;
 }
 __host__ __device__ constexpr bool pad_global(int m) {
     return m == PAD_GLOBAL || m == PAD_GLOBAL_MIN || m == PAD_GLOBAL_MAX;

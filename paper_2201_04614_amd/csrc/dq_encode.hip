@@ -309,6 +309,8 @@ __device__ __forceinline__ uint32_t enc_block_end(const EncArgs& a, EncState<DIM
     uint32_t peff = 0;
     if (pad_global(pad)) {
         peff = gpad;
+    } else if (pad == PAD_GIVEN) {
+        peff = gvalid ? (uint32_t)a.pads[blk] : 0u;
     } else if (pad == PAD_BLOCK_MIN || pad == PAD_BLOCK_MAX) {
         const int32_t P = pad == PAD_BLOCK_MIN ? group_min32<C::GPB>(st.vmin) : group_max32<C::GPB>(st.vmax);
         peff = (uint32_t)P;
@@ -623,6 +625,8 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
             uint32_t peff = 0;
             if (pad_global(a.pad_mode)) {
                 peff = gpad;
+            } else if (a.pad_mode == PAD_GIVEN) {
+                peff = (uint32_t)a.pads[bx];
             } else if (a.pad_mode == PAD_BLOCK_MIN || a.pad_mode == PAD_BLOCK_MAX) {
                 const int32_t P = a.pad_mode == PAD_BLOCK_MIN ? group_min32<64>(vmin) : group_max32<64>(vmax);
                 peff = (uint32_t)P;

@@ -13,13 +13,17 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_compress(x, eb, eb_mode, block, pad, radius, out_cap=None, x_dev=None, vec=0):
-    """Compress on the GPU; returns host copies of everything."""
+def gpu_compress(x, eb, eb_mode, block, pad, radius, out_cap=None, x_dev=None, vec=0, pads=None):
+    """Compress on the GPU; returns host copies of everything. pads: the
+    per-block values of the "given" padding mode."""
     import torch
     if x_dev is None:
         x_dev = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     codec = dq.Codec(x.shape, eb, eb_mode, block, pad, radius,
                      out_cap=x.size if out_cap is None else out_cap, vec=vec)
+    if pads is not None:
+        pv = torch.from_numpy(np.ascontiguousarray(pads, dtype=np.int32).reshape(-1))
+        codec.pads[:pv.numel()].copy_(pv)
     codec.compress_async(x_dev)
     r = codec.result()
     n = int(r.n_out)
@@ -66,12 +70,12 @@ def assert_same_compress(g, c, ctx=""):
 
 
 def parity(ref, x, eb, eb_mode="abs", block=16, pad="zero", radius=512, nthreads=0,
-           check_decode=True, x_dev=None, vec=0):
+           check_decode=True, x_dev=None, vec=0, pads=None):
     """Full comparison of compress and decompress; returns the oracle result."""
     ctx = f"shape={x.shape} eb={eb} {eb_mode} B={block} pad={pad} R={radius}"
     p = ref.params(x.shape, eb, eb_mode, block, pad, radius)
-    c = ref.compress(p, x, nthreads=nthreads)
-    g = gpu_compress(x, eb, eb_mode, block, pad, radius, x_dev=x_dev, vec=vec)
+    c = ref.compress(p, x, nthreads=nthreads, pads=pads)
+    g = gpu_compress(x, eb, eb_mode, block, pad, radius, x_dev=x_dev, vec=vec, pads=pads)
     assert_same_compress(g, c, ctx)
     if c.status == 0 and check_decode:
         st, xr = ref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads, nthreads=nthreads)

@@ -1,5 +1,5 @@
-"""C ABI of libdq: loads without a GPU, exports every symbol include/dq.h
-declares, and validates parameters on the host (no compute calls)."""
+"""C ABI of libdq: loads without a GPU, exports every symbol include/*.h
+declare, and validates parameters on the host (no compute calls)."""
 
 import ctypes as C
 import os
@@ -21,14 +21,20 @@ def L():
 
 
 def declared_functions():
-    with open(os.path.join(ROOT, "include", "dq.h")) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dq_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        with open(os.path.join(ROOT, "include", h)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(dq_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_lists_every_export():
-    assert declared_functions() == sorted(dq.EXPORTS)
+    from paper_2201_04614_amd import selector as SEL
+    assert declared_functions() == sorted(dq.EXPORTS + SEL.EXPORTS)
 
 
 def test_library_exports_every_declared_symbol(L):
@@ -46,7 +52,7 @@ def test_validate_host_only(L):
     ok = dq.make_params((10, 10), 1e-3, "abs", 4, "zero", 512)
     assert dq.validate(ok) == dq.DQ_OK
     bad = [dict(shape=(0, 10)), dict(eb=0.0), dict(eb=float("nan")), dict(eb=1e-320),
-           dict(block=0), dict(pad=8), dict(pad=-1), dict(radius=0), dict(radius=32769), dict(eb_mode=3),
+           dict(block=0), dict(pad=9), dict(pad=-1), dict(radius=0), dict(radius=32769), dict(eb_mode=3),
            dict(shape=(65536, 65536))]
     base = dict(shape=(10, 10), eb=1e-3, eb_mode="abs", block=4, pad="zero", radius=512)
     for b in bad:

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import gpu_util as G
+import npref as NP
 from paper_2201_04614_amd import binding as dq
 from paper_2201_04614_amd import fields as F
 
@@ -157,6 +158,21 @@ def test_radius_extremes_and_heavy_outliers(ref, R):
         x = F.uniform_field(shape, seed=R, lo=-100.0, hi=100.0)
         for pad in ("zero", "edge_mean"):
             G.parity(ref, x, 1e-4, "abs", B, pad, R)
+
+
+@pytest.mark.parametrize("shape,B", [((5000,), 16), ((4099,), 1024), ((37, 61), 8), ((64, 200), 128),
+                                     ((13, 17, 19), 4), ((33, 40, 44), 8)])
+def test_given_pads(ref, shape, B):
+    """Per-block values chosen by the caller: random values, and the values
+    that make every block origin exact."""
+    x = F.uniform_field(shape, seed=sum(shape) + B, lo=-30.0, hi=40.0)
+    eb = 2e-3
+    p = ref.params(shape, eb, "abs", B, "given", 512)
+    nb = ref.pad_count(p)
+    rng = np.random.default_rng(B)
+    G.parity(ref, x, eb, "abs", B, "given", 512, pads=rng.integers(-20000, 20000, size=nb))
+    st, q = ref.prequantize(p, x, eb)
+    G.parity(ref, x, eb, "abs", B, "given", 512, pads=q[NP.origin_mask(shape, B)])
 
 
 def test_wrapping_extremes(ref):

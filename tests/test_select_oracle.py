@@ -1,4 +1,4 @@
-"""Pins of the selector oracle (oracle/select.py) against what the C oracle and
+"""Pins of the selector oracle (oracle/selector.py) against what the C oracle and
 the mathematics fix independently of it."""
 
 import math
@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import npref as NP
-from oracle import select as S
+from oracle import selector as S
 from paper_2201_04614_amd import fields as F
 
 SHAPES = [((203,), 8), ((37, 41), 4), ((21, 18, 27), 4), ((24, 20, 16), 8), ((19, 33, 17), 16)]
@@ -151,3 +151,11 @@ def test_mlp_zero_network_and_adam_first_step():
     th, m, v = S.adam_step(np.zeros_like(g), np.zeros_like(g), np.zeros_like(g), g, 1, 1e-3)
     # first step: m_hat = g, v_hat = g^2, so the update is lr * g / (|g| + eps)
     assert np.allclose(th, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_bf16_rounding_worked_values():
+    """bfloat16 keeps 7 fraction bits: at [1, 2) its step is 2^-7; exact ties
+    go to the even neighbour."""
+    v = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9, 1 + 2 ** -7 + 2 ** -8, -2.5, 0.1], dtype=np.float32)
+    want = np.array([1.0, 1.0, 1 + 2 ** -7, 1 + 2 ** -6, -2.5, 0.10009765625], dtype=np.float32)
+    assert np.array_equal(S.bf16_round(v), want)
