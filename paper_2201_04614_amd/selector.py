@@ -157,23 +157,40 @@ def resolve_eb(x_dev, eb, eb_mode):
 
 @dataclass
 class Search:
-    """Exhaustive search of one field (device tensors unless noted)."""
+    """Exhaustive search of one field (device tensors unless noted); the
+    per-edge dicts are keyed by the block edge."""
     eb_abs: float
-    base: int                 # block edge of the per-block samples
-    info: BlockInfo           # of the base edge
-    zero_out: int             # outliers with zero padding at the base edge (host)
-    best_out: int             # outliers with the best candidate of every block (host)
-    super_cost: object        # int64 [3, n_super]: side cost per block edge (8 * outliers + 4 * pads)
+    base: int                 # block edge of info / zero_out / best_out / sample_bsz
+    infos: dict               # BlockInfo per edge
+    zero_outs: dict           # outliers with zero padding per edge (host)
+    best_outs: dict           # outliers with the best candidate of every block, per edge (host)
+    super_cost: object        # int64 [3, n_super]: side cost per edge (8 * outliers + 4 * pads)
     super_label: object       # int64 [n_super]: best edge index (ties to the larger edge)
-    sample_bsz: object        # int32 [nb]: super-block label of every base block
+    sample_bszs: dict         # int32 [nb]: super-block label of every block, per edge
+
+    @property
+    def info(self):
+        return self.infos[self.base]
+
+    @property
+    def zero_out(self):
+        return self.zero_outs[self.base]
+
+    @property
+    def best_out(self):
+        return self.best_outs[self.base]
+
+    @property
+    def sample_bsz(self):
+        return self.sample_bszs[self.base]
 
 
 def exhaustive_search(x_dev, eb, eb_mode, radius, base=8, stream=None):
-    """Best candidate pad per block (base edge) and best block edge per super-block."""
+    """Best candidate pad per block (every edge) and best block edge per super-block."""
     torch = _torch()
     shape = tuple(x_dev.shape)
     eb_abs = resolve_eb(x_dev, eb, eb_mode)
-    costs, base_info, zero_out, best_out = [], None, None, None
+    costs, infos, zero_outs, best_outs = [], {}, {}, {}
     for B in BSIZES:
         codec = dq.Codec(shape, eb_abs, "abs", B, "zero", radius, out_cap=0, device=x_dev.device)
         codec.compress_async(x_dev, stream=stream)
@@ -181,20 +198,19 @@ def exhaustive_search(x_dev, eb, eb_mode, radius, base=8, stream=None):
         if r.status not in (dq.DQ_OK, dq.DQ_ECAPACITY):
             raise dq.DQError(r.status, f"zero-pad compression, block {B}")
         info = block_features(x_dev, eb_abs, B, radius, codes=codec.codes, stream=stream)
+        del codec
         costs.append(super_cost(shape, B, info, info.label, stream))
-        if B == base:
-            base_info = info
-            zero_out = int(r.n_out)
-            st = info.stats_host()
-            fl = info.flags.cpu().numpy()
-            lab = info.label.cpu().numpy()
-            best_out = int(st["nonorig"].astype(np.int64).sum() + ((fl >> lab) & 1).astype(np.int64).sum())
+        infos[B] = info
+        zero_outs[B] = int(r.n_out)
+        st = info.stats_host()
+        fl = info.flags.cpu().numpy()
+        lab = info.label.cpu().numpy()
+        best_outs[B] = int(st["nonorig"].astype(np.int64).sum() + ((fl >> lab) & 1).astype(np.int64).sum())
     cost = torch.stack(costs)
     # ties keep the larger edge: scan from the largest
-    order = torch.flip(cost, dims=[0])
-    lab = (len(BSIZES) - 1) - torch.argmin(order, dim=0)
-    sample = _super_of_blocks(shape, base, x_dev.device)
-    return Search(eb_abs, base, base_info, zero_out, best_out, cost, lab, lab[sample].to(torch.int32))
+    lab = (len(BSIZES) - 1) - torch.argmin(torch.flip(cost, dims=[0]), dim=0)
+    samples = {B: lab[_super_of_blocks(shape, B, x_dev.device)].to(torch.int32) for B in BSIZES}
+    return Search(eb_abs, base, infos, zero_outs, best_outs, cost, lab, samples)
 
 
 def _super_of_blocks(shape, B, device):

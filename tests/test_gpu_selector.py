@@ -133,7 +133,8 @@ def test_bf16_inference():
 
 def _training_fields(n, shape, seed):
     """Seeded fields where the padding matters: k^-2..k^-4 backgrounds with
-    offsets of up to a few ranges and large-scale ramps."""
+    offsets of up to a few ranges and large-scale ramps (with radius 64 a
+    single global value cannot predict every origin)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
@@ -141,7 +142,7 @@ def _training_fields(n, shape, seed):
         x = F.power_law_grf(shape, slope=slope, seed=int(seed * 1000 + i)).astype(np.float64)
         ramp = rng.normal(0, 1.0, size=3)
         g = np.meshgrid(*[np.linspace(-1, 1, s) for s in shape], indexing="ij")
-        x += sum(r * gi for r, gi in zip(ramp, g)) * float(rng.uniform(0, 3))
+        x += sum(r * gi for r, gi in zip(ramp, g)) * float(rng.uniform(0, 12))
         x += float(rng.choice([0.0, 0.5, 2.0, 5.0])) * (x.max() - x.min())
         out.append((x.astype(np.float32), float(10 ** rng.uniform(-3, -2))))
     return out
@@ -152,7 +153,7 @@ def test_learned_padding_gain(ref):
     keep >= 95 % of the exhaustive search's outlier reduction over zero padding
     on held-out fields, and decode exactly (given mode)."""
     import torch
-    R, B = 512, 8
+    R, B = 64, 8
     Xs, yps, ybs = [], [], []
     G.say("selector: labels of 48 training fields 64^3")
     for x, eb in _training_fields(48, (64, 64, 64), 1):
@@ -177,6 +178,7 @@ def test_learned_padding_gain(ref):
         zero_tot += s.zero_out
         best_tot += s.best_out
         learned_tot += c.n_out
-    G.say(f"selector: zero {zero_tot} exhaustive {best_tot} learned {learned_tot}")
+    G.say(f"selector: zero {zero_tot} exhaustive {best_tot} learned {learned_tot} labels {np.bincount(yp.cpu().numpy(), minlength=5)}")
     assert best_tot < zero_tot
+    assert (yp != 0).float().mean() > 0.2 and (yp > 1).float().mean() > 0.02  # not a one-candidate problem
     assert zero_tot - learned_tot >= 0.95 * (zero_tot - best_tot)
