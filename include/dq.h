@@ -167,6 +167,21 @@ dq_status dq_decompress(const dq_params *p, double eb_abs, const uint16_t *codes
                         void *ws, uint64_t ws_bytes, void *hip_stream,
                         const dq_hooks *hooks);
 
+/* Decompress the stream written by a dq_compress call enqueued earlier on the
+ * same stream (or ordered before this one), taking the outlier count and the
+ * absolute bound from that call's device-resident result cres instead of the
+ * host: no synchronisation between the two calls, and both can be captured
+ * in one HIP graph. out_cap is the capacity given to that compress call (the
+ * outlier buffers hold that many entries). If cres->status is not DQ_OK,
+ * res->status receives it and x_hat is not written. Otherwise as
+ * dq_decompress; ws is needed whenever out_cap > 0. Enqueues one more
+ * (one-thread) kernel that clears res's status word first, so that a replayed
+ * graph reports each replay's own outcome. */
+dq_status dq_decompress_dev(const dq_params *p, const dq_result *cres, uint64_t out_cap,
+                            const uint16_t *codes, const uint32_t *out_idx, const int32_t *out_val,
+                            const int32_t *pads, float *x_hat, dq_result *res, void *ws,
+                            uint64_t ws_bytes, void *hip_stream, const dq_hooks *hooks);
+
 /* Copy a device dq_result to the host after waiting for hip_stream. */
 dq_status dq_result_sync(const dq_result *res_dev, dq_result *res_host, void *hip_stream);
 

@@ -1,0 +1,66 @@
+/*
+ * dq_batch.h - many fields, one HIP graph launch (libdq).
+ *
+ * A batch of fields of different shapes, bounds, blocks and paddings is
+ * compressed and decompressed by one graph: every field's dq_compress and
+ * dq_decompress_dev (which takes the outlier count and bound from the
+ * compress result on the device) are captured once, spread over parallel
+ * branches (largest fields first, each to the least loaded branch), and the
+ * instantiated graph is launched as often as wanted. The fields' buffers are
+ * bound at creation: a launch reads the current contents of every x and
+ * rewrites every output. Blocks are compressed independently (Section III-A),
+ * so the fields need no ordering among themselves.
+ *
+ * Callers: batch pipelines and serving loops that launch the same set of
+ * buffers repeatedly. Memory: every pointer in dq_batch_field is a DEVICE
+ * pointer owned by the caller, sized as for dq_compress / dq_decompress; the
+ * graph handle is host memory owned by the library until
+ * dq_batch_graph_destroy. The parameters are copied at creation.
+ */
+#ifndef DQ_BATCH_H
+#define DQ_BATCH_H
+
+#include <stdint.h>
+
+#include "dq.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    dq_params p;
+    const float *x;     /* field */
+    uint16_t *codes;
+    uint32_t *out_idx;
+    int32_t *out_val;
+    uint64_t out_cap;
+    int32_t *pads;      /* read instead of written for DQ_PAD_GIVEN */
+    dq_result *cres;    /* compress result */
+    void *cws;
+    uint64_t cws_bytes;
+    float *x_hat;       /* NULL: compress only */
+    dq_result *dres;    /* decompress result */
+    void *dws;
+    uint64_t dws_bytes;
+} dq_batch_field;
+
+typedef struct dq_batch_graph dq_batch_graph;
+
+/* Capture the batch (n >= 1 fields) over `branches` parallel branches
+ * (1..16) into a graph. Host-side errors of any field (as dq_compress /
+ * dq_decompress_dev would return them) abort the creation and are returned;
+ * DQ_EDEVICE if a HIP call fails. */
+dq_status dq_batch_graph_create(const dq_batch_field *fields, uint64_t n, int branches,
+                                dq_batch_graph **graph);
+
+/* Enqueue one execution of the graph on hip_stream. Per-field outcomes land
+ * in each field's cres / dres. */
+dq_status dq_batch_graph_launch(dq_batch_graph *graph, void *hip_stream);
+
+dq_status dq_batch_graph_destroy(dq_batch_graph *graph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

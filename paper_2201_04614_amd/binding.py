@@ -23,7 +23,7 @@ PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
 
 # every function include/dq.h declares
 EXPORTS = ["dq_validate", "dq_num_blocks", "dq_pad_count", "dq_compress_workspace",
-           "dq_decompress_workspace", "dq_compress", "dq_decompress", "dq_result_sync",
+           "dq_decompress_workspace", "dq_compress", "dq_decompress", "dq_decompress_dev", "dq_result_sync",
            "dq_event_create", "dq_event_destroy", "dq_event_elapsed_ms", "dq_strerror"]
 
 
@@ -69,6 +69,7 @@ def lib():
             "dq_compress": ([P, vp, vp, vp, vp, u64, vp, vp, vp, u64, vp, C.POINTER(Hooks)], C.c_int),
             "dq_decompress": ([P, C.c_double, vp, vp, vp, u64, vp, vp, vp, vp, u64, vp,
                                C.POINTER(Hooks)], C.c_int),
+            "dq_decompress_dev": ([P, vp, u64, vp, vp, vp, vp, vp, vp, vp, u64, vp, C.POINTER(Hooks)], C.c_int),
             "dq_result_sync": ([vp, C.POINTER(Result), vp], C.c_int),
             "dq_event_create": ([C.POINTER(C.c_void_p)], C.c_int),
             "dq_event_destroy": ([vp], C.c_int),
@@ -267,6 +268,9 @@ class Codec:
         codes = self.codes if codes is None else codes
         out_idx = self.out_idx if out_idx is None else out_idx
         out_val = self.out_val if out_val is None else out_val
+        # the kernels read n_out entries of both lists: never more than they hold
+        if int(n_out) > min(out_idx.numel(), out_val.numel()) or (out_idx is self.out_idx and int(n_out) > self.out_cap):
+            raise DQError(DQ_EINVAL, f"dq_decompress: n_out {int(n_out)} exceeds the outlier buffers")
         pads = self.pads if pads is None else pads
         out = self.x_hat if out is None else out
         st = lib().dq_decompress(C.byref(self.p), float(eb_abs), _ptr(codes), _ptr(out_idx),
@@ -275,6 +279,18 @@ class Codec:
                                  C.byref(hooks.struct) if hooks else None)
         if st != DQ_OK:
             raise DQError(st, "dq_decompress")
+        return out
+
+    def decompress_dev_async(self, out=None, stream=None, hooks=None):
+        """Enqueue decompression of this codec's last compression, taking the
+        outlier count and bound from its device result (no host sync)."""
+        out = self.x_hat if out is None else out
+        st = lib().dq_decompress_dev(C.byref(self.p), _ptr(self.res), self.out_cap, _ptr(self.codes),
+                                     _ptr(self.out_idx), _ptr(self.out_val), _ptr(self.pads), _ptr(out),
+                                     _ptr(self.dres), _ptr(self.ws_d), self.ws_d.numel(), _stream_handle(stream),
+                                     C.byref(hooks.struct) if hooks else None)
+        if st != DQ_OK:
+            raise DQError(st, "dq_decompress_dev")
         return out
 
     def decompress_result(self, stream=None):

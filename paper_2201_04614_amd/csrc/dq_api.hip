@@ -301,37 +301,50 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     return check_launch();
 }
 
-dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes, const uint32_t* out_idx,
-                        const int32_t* out_val, uint64_t n_out, const int32_t* pads, float* x_hat,
-                        dq_result* res, void* ws, uint64_t ws_bytes, void* hip_stream,
-                        const dq_hooks* hooks) {
+}  // extern "C"
+
+namespace {
+
+// Shared by dq_decompress (host count and bound) and dq_decompress_dev (both
+// read on the device from the compress result src; cap = its capacity).
+dq_status decompress_impl(const dq_params* p, double eb_abs, uint64_t n_out, const dq_result* src, uint64_t cap,
+                          const uint16_t* codes, const uint32_t* out_idx, const int32_t* out_val,
+                          const int32_t* pads, float* x_hat, dq_result* res, void* ws, uint64_t ws_bytes,
+                          void* hip_stream, const dq_hooks* hooks) {
     dq_status st = validate(p, false);
     if (st != DQ_OK) return st;
-    if (!(eb_abs > 0.0) || !isfinite(eb_abs)) return DQ_EINVAL;
+    if (!src && (!(eb_abs > 0.0) || !isfinite(eb_abs))) return DQ_EINVAL;
     uint64_t npads = 0;
     dq_pad_count(p, &npads);
     if (!codes || !x_hat || !res) return DQ_EINVAL;
     if ((reinterpret_cast<uintptr_t>(res) % 8) != 0) return DQ_EINVAL;  // one 64-bit status word
-    if (n_out > 0 && (!out_idx || !out_val || !ws)) return DQ_EINVAL;
+    if (src && (reinterpret_cast<uintptr_t>(src) % 8) != 0) return DQ_EINVAL;
+    const uint64_t most = src ? cap : n_out;  // the largest count the kernels may see
+    if (most > 0 && (!out_idx || !out_val || !ws)) return DQ_EINVAL;
     if (npads > 0 && !pads) return DQ_EINVAL;
     Plan pl;
     if (!make_plan(p, x_hat, codes, pl)) return DQ_ENOTSUP;
     if (n_out > pl.g.N) return DQ_EINVAL;
+    const uint64_t capn = cap < pl.g.N ? cap : pl.g.N;
     uint64_t need = 0;
     dq_decompress_workspace(p, &need);
-    if (n_out > 0 && ws_bytes < need) return DQ_EINVAL;
+    if (most > 0 && ws_bytes < need) return DQ_EINVAL;
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     uint32_t* block_start = static_cast<uint32_t*>(ws);
     const uint32_t tag = next_tag();
-    if (n_out > 0)
-        launch_index(out_idx, (uint32_t)n_out, pl.g, ilog2((uint32_t)pl.B), pl.dim, block_start, res, tag, stream);
+    if (src) launch_result_reset(res, stream);
+    if (src ? capn > 0 : n_out > 0)
+        launch_index(out_idx, (uint32_t)n_out, pl.g, ilog2((uint32_t)pl.B), pl.dim, block_start, res, tag, stream,
+                     src, (uint32_t)capn);
 
     DecArgs da;
+    da.src = reinterpret_cast<const ResultView*>(src);
+    da.cap = (uint32_t)capn;
     da.res_word = reinterpret_cast<unsigned long long*>(res);
     da.n_out_out = reinterpret_cast<unsigned long long*>(&res->n_out);
     da.eb_out = &res->eb_abs;
-    da.eb_abs = eb_abs;
+    da.eb_abs = src ? 1.0 : eb_abs;
     da.tag = tag;
     da.codes = codes;
     da.out_idx = out_idx;
@@ -340,7 +353,7 @@ dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes
     da.block_start = block_start;
     da.x_hat = x_hat;
     da.g = pl.g;
-    da.twoeb = 2.0 * eb_abs;
+    da.twoeb = 2.0 * da.eb_abs;
     da.n_out = (uint32_t)n_out;
     da.R = p->radius;
     da.pad_mode = p->pad_mode;
@@ -349,6 +362,26 @@ dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes
     if (!launch_decode(pl.dim, pl.B, pl.V, da, grid, stream)) return DQ_ENOTSUP;
     if (hooks && hooks->ev_after) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_after), stream);
     return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+dq_status dq_decompress(const dq_params* p, double eb_abs, const uint16_t* codes, const uint32_t* out_idx,
+                        const int32_t* out_val, uint64_t n_out, const int32_t* pads, float* x_hat,
+                        dq_result* res, void* ws, uint64_t ws_bytes, void* hip_stream,
+                        const dq_hooks* hooks) {
+    return decompress_impl(p, eb_abs, n_out, nullptr, 0, codes, out_idx, out_val, pads, x_hat, res, ws, ws_bytes,
+                           hip_stream, hooks);
+}
+
+dq_status dq_decompress_dev(const dq_params* p, const dq_result* cres, uint64_t out_cap, const uint16_t* codes,
+                            const uint32_t* out_idx, const int32_t* out_val, const int32_t* pads, float* x_hat,
+                            dq_result* res, void* ws, uint64_t ws_bytes, void* hip_stream, const dq_hooks* hooks) {
+    if (!cres) return DQ_EINVAL;
+    return decompress_impl(p, 0.0, 0, cres, out_cap, codes, out_idx, out_val, pads, x_hat, res, ws, ws_bytes,
+                           hip_stream, hooks);
 }
 
 dq_status dq_result_sync(const dq_result* res_dev, dq_result* res_host, void* hip_stream) {

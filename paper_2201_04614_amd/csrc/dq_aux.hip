@@ -445,9 +445,14 @@ __device__ __forceinline__ void cell_block(const IndexGeom& ig, uint32_t idx, ui
 // outliers must be in strictly increasing (block, local row-major) order.
 __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_idx, uint32_t n_out,
                                                IndexGeom ig, uint32_t* __restrict__ block_start,
-                                               unsigned long long* res_word, uint32_t tag) {
+                                               unsigned long long* res_word, uint32_t tag,
+                                               const ResultView* src, uint32_t cap) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t N = ig.g.N;
+    if (src) {  // the count of the compress call that wrote the list (at most its capacity)
+        const unsigned long long n = src->n_out;
+        n_out = (uint32_t)(n < cap ? n : cap);
+    }
     if (i < n_out) {
         const uint32_t idx = out_idx[i];
         bool ok = idx < N;
@@ -479,12 +484,24 @@ __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_
 }
 
 void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
-                  uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream) {
+                  uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream, const void* src,
+                  uint32_t cap) {
     IndexGeom ig{g, (uint32_t)block_log2, (uint32_t)dim};
-    const uint64_t work = n_out > (uint64_t)g.nblocks + 1 ? (uint64_t)n_out : (uint64_t)g.nblocks + 1;
+    const uint64_t cnt = src ? (uint64_t)cap : (uint64_t)n_out;  // with src: the largest possible count
+    const uint64_t work = cnt > (uint64_t)g.nblocks + 1 ? cnt : (uint64_t)g.nblocks + 1;
     const uint32_t blocks = (uint32_t)((work + 255) / 256);
     hipLaunchKernelGGL(k_index, dim3(blocks), dim3(256), 0, stream, out_idx, n_out, ig, block_start,
-                       reinterpret_cast<unsigned long long*>(res), tag);
+                       reinterpret_cast<unsigned long long*>(res), tag, (const ResultView*)src, cap);
+}
+
+// Clears a result's status word (tag 0 is never a call's tag), so that a
+// decompress enqueued again with the same tag (a replayed graph) starts clean.
+__global__ void k_result_reset(unsigned long long* w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *w = 0ull;
+}
+
+void launch_result_reset(void* res, hipStream_t stream) {
+    hipLaunchKernelGGL(k_result_reset, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned long long*>(res));
 }
 
 }  // namespace dq

@@ -237,6 +237,21 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kWaves + wave;
+    if (a.src) {  // the outlier count and bound of the compress call that wrote this stream
+        const int sst = (int)uniform((uint32_t)a.src->status);
+        const unsigned long long n = a.src->n_out;
+        a.eb_abs = uniform(a.src->eb_abs);
+        a.twoeb = 2.0 * a.eb_abs;
+        a.n_out = uniform((uint32_t)(n < a.cap ? n : a.cap));
+        if (sst != ST_OK) {  // nothing valid to decode: pass the compress status on
+            if (t == 0 && lane == 0) {
+                *a.n_out_out = n;
+                *a.eb_out = a.eb_abs;
+                status_set_tagged(a.res_word, a.tag, sst);
+            }
+            return;
+        }
+    }
     if (t == 0 && lane == 0) {  // the call's result (status: see status_init_tagged)
         *a.n_out_out = a.n_out;
         *a.eb_out = a.eb_abs;

@@ -168,7 +168,22 @@ __device__ __forceinline__ void status_corrupt_tagged(unsigned long long* w, uin
                                 __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Read-only view of a dq_result written by an earlier compress call.
+struct ResultView {
+    int32_t status;
+    uint32_t reserved;
+    unsigned long long n_out;
+    double eb_abs;
+};
+
+__device__ __forceinline__ void status_set_tagged(unsigned long long* w, uint32_t tag, int st) {
+    (void)__hip_atomic_exchange(w, ((unsigned long long)tag << 32) | (uint32_t)st, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct DecArgs {
+    const ResultView* src;         // non-null: n_out / eb_abs come from this compress result
+    uint32_t cap;                  // with src: the out_cap of that compress call
     unsigned long long* res_word;  // dq_result status + reserved (tagged, see above)
     unsigned long long* n_out_out; // dq_result.n_out
     double* eb_out;                // dq_result.eb_abs

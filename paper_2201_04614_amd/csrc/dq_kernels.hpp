@@ -96,6 +96,8 @@ void launch_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out
                   uint32_t n_tiles, const uint32_t* block_info, Geom g, uint32_t* out_idx, int32_t* out_val,
                   hipStream_t stream);
 void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
-                  uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream);
+                  uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream, const void* src = nullptr,
+                  uint32_t cap = 0);
+void launch_result_reset(void* res, hipStream_t stream);
 
 }  // namespace dq
