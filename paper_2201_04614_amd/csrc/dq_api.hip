@@ -132,9 +132,9 @@ uint64_t max_tiles(const dq_params* p) {
 
 // Compress workspace: scalars, value-range partials, per-tile counts and
 // offsets, per-chunk count sums, per-block outlier prefixes, then the outlier
-// staging area: per-tile regions of at most cap / 2 entries in all, and an
-// overflow list of cap entries (the overflow never exceeds the outlier count,
-// so everything fits whenever the outliers fit the caller's capacity).
+// staging area: per-tile regions of cap entries in all (cap / tiles each),
+// and an overflow list of cap entries (the overflow never exceeds the outlier
+// count, so everything fits whenever the outliers fit the caller's capacity).
 struct CompressLayout {
     uint64_t sc, parts, tiles, toff, csum, info, region, ovf, cap, total;
 };
@@ -153,7 +153,7 @@ CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     L.csum = L.toff + align_up(4 * mt);
     L.info = L.csum + align_up(4 * ((mt + kChunkTiles - 1) / kChunkTiles));
     L.region = L.info + align_up(4ull * g.nblocks);
-    L.ovf = L.region + align_up(16 * (cap / 2));
+    L.ovf = L.region + align_up(16 * cap);
     L.total = L.ovf + align_up(16 * (cap > 0 ? cap : 1));
     return L;
 }
@@ -255,7 +255,7 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     uint32_t* toff = reinterpret_cast<uint32_t*>(w + L.toff);
     uint32_t* info = reinterpret_cast<uint32_t*>(w + L.info);
     Staging stg;
-    stg.spt = (uint32_t)((cap / 2) / pl.g.n_tiles);
+    stg.spt = (uint32_t)(cap / pl.g.n_tiles);
     stg.region = reinterpret_cast<uint4*>(w + L.region);
     stg.ovf = reinterpret_cast<uint4*>(w + L.ovf);
     stg.ovf_cap = (uint32_t)cap;

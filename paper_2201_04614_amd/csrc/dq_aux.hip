@@ -441,6 +441,21 @@ __device__ __forceinline__ void cell_block(const IndexGeom& ig, uint32_t idx, ui
     local = (((z & m) << ig.lb | (y & m)) << ig.lb) | (x & m);
 }
 
+// First position in [lo, hi) of the outlier list whose block is >= b (hi if
+// none); an index outside the field counts as past every block.
+__device__ __forceinline__ uint32_t first_at_or_after(const uint32_t* __restrict__ out_idx, uint32_t lo, uint32_t hi,
+                                                      uint32_t b, const IndexGeom& ig) {
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const uint32_t idx = out_idx[mid];
+        uint32_t bb = 0xffffffffu, l;
+        if (idx < ig.g.N) cell_block(ig, idx, bb, l);
+        if (bb < b) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // block_start[b] = first outlier of block b or later (b = 0..n_blocks);
 // outliers must be in strictly increasing (block, local row-major) order.
 __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_idx, uint32_t n_out,
@@ -469,17 +484,18 @@ __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_
         }
         if (!ok) status_corrupt_tagged(res_word, tag);
     }
-    if (i <= ig.g.nblocks) {
-        uint32_t lo = 0, hi = n_out;
-        while (lo < hi) {
-            const uint32_t mid = lo + (hi - lo) / 2;
-            const uint32_t idx = out_idx[mid];
-            uint32_t b = 0xffffffffu, l;
-            if (idx < N) cell_block(ig, idx, b, l);
-            if (b < i) lo = mid + 1;
-            else hi = mid;
+    // block_start of the workgroup's 256 blocks: two searches over the whole
+    // list bound the range in which all of them lie, then every thread
+    // searches that (short, cache-resident) range
+    __shared__ uint32_t range[2];
+    const uint32_t b0 = blockIdx.x * blockDim.x;
+    if (b0 <= ig.g.nblocks) {  // uniform in the workgroup
+        if (threadIdx.x < 2) {
+            const uint32_t target = threadIdx.x == 0 ? b0 : min(b0 + blockDim.x, ig.g.nblocks + 1);
+            range[threadIdx.x] = first_at_or_after(out_idx, 0, n_out, target, ig);
         }
-        block_start[i] = lo;
+        __syncthreads();
+        if (i <= ig.g.nblocks) block_start[i] = first_at_or_after(out_idx, range[0], range[1], i, ig);
     }
 }
 

@@ -220,6 +220,38 @@ def sharp_feature_field_device(shape=(512, 1024, 1024), seed=5, n_planes=25, n_s
     return f.contiguous()
 
 
+def power_law_grf_device(shape, slope=3.0, seed=0, device="cuda"):
+    """Gaussian random field with power spectrum |k|^-slope of any dimension
+    (1-3), synthesised on a GPU with torch: seeded white noise, rfftn, the
+    spectrum scaled by |k|^(-slope/2) with integer wavenumbers (k = 0
+    removed), irfftn, zero mean and unit standard deviation. fp32 device
+    tensor, C order; the recipe of power_law_grf on another random stream."""
+    import torch
+
+    shape = tuple(int(s) for s in shape)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    spec = torch.fft.rfftn(torch.randn(shape, generator=gen, device=device, dtype=torch.float32))
+    k2 = None
+    for a, n in enumerate(shape):
+        f = (torch.fft.rfftfreq(n, d=1.0 / n, device=device) if a == len(shape) - 1
+             else torch.fft.fftfreq(n, d=1.0 / n, device=device)).to(torch.float32) ** 2
+        view = [1] * len(shape)
+        view[a] = f.numel()
+        f = f.reshape(view)
+        k2 = f if k2 is None else k2 + f
+    amp = torch.where(k2 > 0, k2.clamp_min(1e-30) ** (-slope / 4.0), torch.zeros_like(k2))
+    spec *= amp
+    del amp, k2
+    x = torch.fft.irfftn(spec, s=shape)
+    del spec
+    x -= x.mean()
+    sd = x.std(correction=0)
+    if float(sd) > 0:
+        x /= sd
+    return x.contiguous()
+
+
 def field_range(x):
     """max - min of a field, in fp64 (used to state eb = c * range)."""
     return float(np.float64(x.max()) - np.float64(x.min()))
