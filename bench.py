@@ -204,7 +204,8 @@ def run_batch(args, W):
     b = BT.Batch(items(tuned), branches=4)
     ms = time_graph(b, args.steps, args.warmup)
     res = b.results()
-    n_out = sum(int(r.n_out) for r, _ in res)
+    per_out = [int(r.n_out) for r, _ in res]
+    n_out = sum(per_out)
     # the same calls enqueued one by one on one stream (no graph)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -239,7 +240,9 @@ def run_batch(args, W):
         "outlier_pct": round(100.0 * n_out / N, 4),
         "ms_per_step_untuned": round(ms_default, 4), "ms_per_step_no_graph": round(ms_eager, 4),
         "autotune_s": round(t_tune, 2),
-        "tuned": [{"shape": list(s["shape"]), "block": B, "vec": V} for s, (B, V) in zip(specs, tuned)],
+        "tuned": [{"shape": list(s["shape"]), "block": B, "vec": V, "eb_rel": round(s["eb"], 8),
+                   "slope": round(s["slope"], 3), "outlier_pct": round(100.0 * po / n, 3)}
+                  for s, (B, V), po, n in zip(specs, tuned, per_out, [x.numel() for x in xs])],
     }
     print(json.dumps(out), flush=True)
 
