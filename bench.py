@@ -247,6 +247,48 @@ def run_batch(args, W):
     print(json.dumps(out), flush=True)
 
 
+def entropy_report(codecs, pads, n_out, reps=10):
+    """Huffman stage on each mode's codes (outside the timed step): bits per
+    code, compression ratio of the whole stream against fp32, and the GPU
+    times of the codebook, encode and decode."""
+    import torch
+    from paper_2201_04614_amd import binding as dq
+    from paper_2201_04614_amd import huffman as HF
+    out = {}
+    for pi, pad in enumerate(pads):
+        cd = codecs[pi][0]
+        codes = cd.codes.reshape(-1)
+        n = codes.numel()
+        K = 2 * cd.radius
+        ws = HF._ws(n, codes.device)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t = {"codebook": 0.0, "encode": 0.0, "decode": 0.0}
+        for r in range(reps + 1):
+            ev[0].record()
+            cb = HF.codebook(codes, K)
+            ev[1].record()
+            bs = HF.encode(codes, cb, ws=ws)
+            ev[2].record()
+            back, st = HF.decode(bs, cb, ws=ws)
+            ev[3].record()
+            torch.cuda.synchronize()
+            if r:
+                t["codebook"] += ev[0].elapsed_time(ev[1]) / reps
+                t["encode"] += ev[1].elapsed_time(ev[2]) / reps
+                t["decode"] += ev[2].elapsed_time(ev[3]) / reps
+        assert int(cb.status.item()) == 0 and int(bs.status.item()) == 0 and int(st.item()) == 0
+        assert torch.equal(back, codes)
+        words = int(bs.chunk_off[-1].item())
+        nch = bs.chunk_off.numel() - 1
+        stream = 4 * words + 8 * (nch + 1) + K + 8 * n_out[pad] + 4 * dq.pad_count(cd.p) + 64
+        out[pad] = {"bits_per_code": round(32.0 * words / n, 4), "ratio_vs_fp32": round(4.0 * n / stream, 3),
+                    "codebook_ms": round(t["codebook"], 4), "encode_ms": round(t["encode"], 4),
+                    "decode_ms": round(t["decode"], 4),
+                    "encode_GBps_of_codes": round(2.0 * n / (t["encode"] * 1e-3) / 1e9, 1),
+                    "decode_GBps_of_codes": round(2.0 * n / (t["decode"] * 1e-3) / 1e9, 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +298,8 @@ def main():
     ap.add_argument("--vec", type=int, default=0, help="cells per lane hint (0 = automatic)")
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--entropy", action="store_true",
+                    help="also time the Huffman stage on each mode's codes and report the compression ratio")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy used to scale the byte counters")
     args = ap.parse_args()
@@ -400,6 +444,9 @@ def main():
         "step_algorithmic_GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "step_pct_hbm_peak": round(100.0 * step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 2),
     }
+    if args.entropy:
+        log("bench: Huffman stage on the codes")
+        out["entropy"] = entropy_report(codecs, PADS, n_out)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(x, W, eb_abs[PADS[0]])

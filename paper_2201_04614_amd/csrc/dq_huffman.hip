@@ -26,6 +26,8 @@ constexpr uint32_t kMaxPresent = DQ_HUFF_MAX_PRESENT;
 constexpr int kMaxLen = 32;
 constexpr int kLutBits = 11;
 constexpr uint32_t kLocalBins = 8192;
+constexpr uint32_t kStage = 16;              // words a decoding thread stages at a time
+constexpr uint64_t kStageMinChunks = 65536;  // staging pays once the chunks fill the GPU
 constexpr int ST_ENOTSUP = DQ_ENOTSUP;
 
 struct DTable {
@@ -53,29 +55,54 @@ __global__ __launch_bounds__(256) void k_huff_zero(uint32_t* p, uint32_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Codes are mostly in a few bins (the residuals of smooth data cluster at
+// the centre): alphabets of at most 2048 symbols get one LDS copy of the bins
+// per wave, larger ones up to kLocalBins one copy per workgroup, beyond that
+// global atomics. vec8: codes are 16-byte aligned, read 8 at a time.
 __global__ __launch_bounds__(256) void k_huff_hist(const uint16_t* __restrict__ codes, uint64_t n, uint32_t K,
-                                                   uint32_t* __restrict__ hist, int32_t* status) {
+                                                   int vec8, uint32_t* __restrict__ hist, int32_t* status) {
     __shared__ uint32_t lh[kLocalBins];
     const bool local = K <= kLocalBins;  // uniform
+    const uint32_t copies = K <= kLocalBins / 4 ? 4u : 1u;
+    uint32_t* mine = lh + (copies == 4u ? (threadIdx.x >> 6) * K : 0u);
     if (local) {
-        for (uint32_t s = threadIdx.x; s < K; s += 256u) lh[s] = 0u;
+        for (uint32_t s = threadIdx.x; s < copies * K; s += 256u) lh[s] = 0u;
         __syncthreads();
     }
     bool bad = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256u) {
-        const uint32_t c = codes[i];
+    auto count = [&](uint32_t c) {
         if (c >= K) {
             bad = true;
         } else if (local) {
-            atomicAdd(&lh[c], 1u);
+            atomicAdd(&mine[c], 1u);
         } else {
             atomicAdd(&hist[c], 1u);
         }
+    };
+    const uint64_t tid = (uint64_t)blockIdx.x * 256u + threadIdx.x, stride = (uint64_t)gridDim.x * 256u;
+    uint64_t done = 0;
+    if (vec8) {
+        const uint4* c8 = reinterpret_cast<const uint4*>(codes);
+        const uint64_t n8 = n / 8;
+        for (uint64_t i = tid; i < n8; i += stride) {
+            const uint4 v = c8[i];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                count(w[k] & 0xffffu);
+                count(w[k] >> 16);
+            }
+        }
+        done = n8 * 8;
     }
+    for (uint64_t i = done + tid; i < n; i += stride) count(codes[i]);
     if (local) {
         __syncthreads();
-        for (uint32_t s = threadIdx.x; s < K; s += 256u)
-            if (lh[s]) atomicAdd(&hist[s], lh[s]);
+        for (uint32_t s = threadIdx.x; s < K; s += 256u) {
+            uint32_t v = 0;
+            for (uint32_t c = 0; c < copies; ++c) v += lh[c * K + s];
+            if (v) atomicAdd(&hist[s], v);
+        }
     }
     if (bad) set_status(status, ST_EINVAL);
 }
@@ -439,13 +466,18 @@ __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict_
     }
 }
 
+// staged: with many chunks (several waves per CU) every thread loads its
+// next kStage words at once into LDS (one latency per ~kStage * 32 bits);
+// with few chunks each thread's serial decoding chain dominates, and it
+// loads the next word one refill ahead in a register instead.
 __global__ __launch_bounds__(256) void k_huff_decode(const uint32_t* __restrict__ words, uint64_t n_words,
                                                      const unsigned long long* __restrict__ chunk_off, uint64_t n,
                                                      const DTable* __restrict__ t, uint16_t* __restrict__ out,
-                                                     int32_t* status) {
+                                                     int32_t* status, int staged) {
     __shared__ uint32_t lut[1u << kLutBits];
     __shared__ uint16_t sorted[kMaxPresent];
     __shared__ uint32_t cnt[kMaxLen + 1], fcode[kMaxLen + 1], fidx[kMaxLen + 1];
+    __shared__ uint32_t stage[256][kStage + 1];
     for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += 256u) lut[i] = t->lut[i];
     const uint32_t np = min(t->n_present, kMaxPresent);
     for (uint32_t i = threadIdx.x; i < np; i += 256u) sorted[i] = t->sorted[i];
@@ -467,12 +499,31 @@ __global__ __launch_bounds__(256) void k_huff_decode(const uint32_t* __restrict_
     int have = 0;
     bool bad = false;
     uint16_t* o = out + c * kChunk;
+    uint32_t* sb = stage[threadIdx.x];
+    uint32_t sidx = kStage;
+    uint32_t pre = 0;
+    if (!staged) {
+        pre = w < wend ? words[w] : 0u;
+        ++w;
+    }
     for (uint32_t i = 0; i < m; ++i) {
         while (have <= 32) {  // keep at least 33 bits: every codeword fits
-            const unsigned long long v = w < wend ? words[w] : 0u;
+            unsigned long long v;
+            if (staged) {
+                if (sidx == kStage) {  // kStage independent loads, one latency
+#pragma unroll
+                    for (uint32_t k = 0; k < kStage; ++k) sb[k] = (w + k < wend) ? words[w + k] : 0u;
+                    w += kStage;
+                    sidx = 0;
+                }
+                v = sb[sidx++];
+            } else {  // the next word was loaded at the previous refill
+                v = pre;
+                pre = w < wend ? words[w] : 0u;
+                ++w;
+            }
             buf |= v << (32 - have);
             have += 32;
-            ++w;
         }
         const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
         uint32_t len = e & 0xffu, sym = e >> 8;
@@ -548,7 +599,9 @@ dq_status dq_huff_codebook(const uint16_t* codes, uint64_t n, uint32_t n_symbols
     hipLaunchKernelGGL(k_huff_zero, dim3((n_symbols + 255) / 256), dim3(256), 0, st, hist, n_symbols);
     uint64_t grid = (n + 256 * 16 - 1) / (256 * 16);
     if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(k_huff_hist, dim3((uint32_t)grid), dim3(256), 0, st, codes, n, n_symbols, hist, status);
+    const int vec8 = (reinterpret_cast<uintptr_t>(codes) % 16) == 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_huff_hist, dim3((uint32_t)grid), dim3(256), 0, st, codes, n, n_symbols, vec8, hist,
+                       status);
     hipLaunchKernelGGL(k_huff_build, dim3(1), dim3(1024), 0, st, (const uint32_t*)hist, n_symbols, lengths,
                        codewords, status);
     return launched();
@@ -593,7 +646,8 @@ dq_status dq_huff_decode(const uint32_t* words, uint64_t n_words, const uint64_t
     hipLaunchKernelGGL(k_huff_status_ok, dim3(1), dim3(64), 0, st, status);
     hipLaunchKernelGGL(k_huff_dtable, dim3(1), dim3(1024), 0, st, lengths, n_symbols, t, status);
     hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)((nch + 255) / 256)), dim3(256), 0, st, words, n_words,
-                       reinterpret_cast<const unsigned long long*>(chunk_off), n, (const DTable*)t, codes, status);
+                       reinterpret_cast<const unsigned long long*>(chunk_off), n, (const DTable*)t, codes, status,
+                       nch >= kStageMinChunks ? 1 : 0);
     return launched();
 }
 
