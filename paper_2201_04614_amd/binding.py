@@ -206,9 +206,27 @@ class DQStream:
     out_idx: object    # torch.int32 tensor holding uint32 indices, n_out entries
     out_val: object    # torch.int32, n_out entries
     pads: object       # torch.int32, pad_count entries
+    coded: object = None  # Huffman-coded codes (HuffCoded) when codes is None
 
     def params(self):
         return make_params(self.shape, self.eb_abs, "abs", self.block, self.pad, self.radius)
+
+    def stream_bytes(self):
+        """Bytes of the stream: codes (raw or coded), outliers, pads, code table."""
+        b = 8 * self.n_out + 4 * self.pads.numel() + 64
+        if self.codes is not None:
+            return b + 2 * self.codes.numel()
+        c = self.coded
+        return b + 4 * c.words.numel() + 8 * c.chunk_off.numel() + c.lengths.numel()
+
+
+@dataclass
+class HuffCoded:
+    """Canonical Huffman coding of a stream's codes (see huffman.py)."""
+    n_symbols: int
+    lengths: object    # torch.uint8 [n_symbols]
+    chunk_off: object  # torch.int64 [n_chunks + 1]
+    words: object      # torch.int32 [words]
 
 
 def result_sync(res_dev, stream=None):
@@ -297,12 +315,13 @@ class Codec:
         return result_sync(self.dres, stream)
 
 
-def compress(x, eb, eb_mode="abs", block=16, pad="zero", radius=512, out_cap=None):
+def compress(x, eb, eb_mode="abs", block=16, pad="zero", radius=512, out_cap=None, entropy=False):
     """Compress a contiguous fp32 CUDA tensor; returns a DQStream.
 
     Raises DQError on a host-side error or a device status other than OK. When
     the outlier capacity is exceeded the call is repeated once with the exact
-    count."""
+    count. entropy=True also Huffman-codes the codes (the stream then holds
+    the coded form instead of the raw codes)."""
     torch = _torch()
     x = x.contiguous()
     codec = Codec(tuple(x.shape), eb, eb_mode, block, pad, radius, out_cap, x.device)
@@ -316,20 +335,42 @@ def compress(x, eb, eb_mode="abs", block=16, pad="zero", radius=512, out_cap=Non
         raise DQError(r.status, "compress")
     n = int(r.n_out)
     npads = pad_count(codec.p)
-    return DQStream(codec.shape, codec.block, codec.pad, codec.radius, float(r.eb_abs), n,
-                    codec.codes, codec.out_idx[:n], codec.out_val[:n], codec.pads[:npads])
+    s = DQStream(codec.shape, codec.block, codec.pad, codec.radius, float(r.eb_abs), n,
+                 codec.codes, codec.out_idx[:n], codec.out_val[:n], codec.pads[:npads])
+    if entropy:
+        from . import huffman as HF
+        flat = codec.codes.reshape(-1)
+        cb = HF.codebook(flat, 2 * codec.radius)
+        bs = HF.encode(flat, cb)
+        st = int(cb.status.item()) or int(bs.status.item())
+        if st != DQ_OK:
+            raise DQError(st, "huffman encode")
+        total = int(bs.chunk_off[-1].item())
+        s.coded = HuffCoded(2 * codec.radius, cb.lengths, bs.chunk_off, bs.words[:total].clone())
+        s.codes = None
+    return s
 
 
 def decompress(s: DQStream, out=None):
     """Decompress a DQStream into an fp32 CUDA tensor of the field's shape."""
     torch = _torch()
     p = s.params()
-    dev = s.codes.device
+    codes = s.codes
+    if codes is None:  # Huffman-coded stream: decode the codes first
+        from . import huffman as HF
+        c = s.coded
+        n = int(np.prod(s.shape))
+        bs = HF.Bitstream(n, c.chunk_off, c.words, None)
+        flat, hst = HF.decode(bs, HF.Codebook(c.n_symbols, None, c.lengths, None, None))
+        if int(hst.item()) != DQ_OK:
+            raise DQError(int(hst.item()), "huffman decode")
+        codes = flat.reshape(s.shape)
+    dev = codes.device
     out = torch.empty(s.shape, dtype=torch.float32, device=dev) if out is None else out
     res = torch.zeros(3, dtype=torch.int64, device=dev)
     ws = _aligned_bytes(decompress_workspace(p), dev)
     pads = s.pads if s.pads.numel() else None
-    st = lib().dq_decompress(C.byref(p), float(s.eb_abs), _ptr(s.codes), _ptr(s.out_idx),
+    st = lib().dq_decompress(C.byref(p), float(s.eb_abs), _ptr(codes), _ptr(s.out_idx),
                              _ptr(s.out_val), int(s.n_out), _ptr(pads), _ptr(out), _ptr(res),
                              _ptr(ws), ws.numel(), _stream_handle(), None)
     if st != DQ_OK:

@@ -120,3 +120,31 @@ def test_error_statuses():
     bs2 = HF.encode(_dev(good), other)
     assert int(bs2.status.item()) == dq.DQ_EINVAL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", ["sinusoid", "grf-rel", "uniform-outliers"])
+def test_end_to_end_stream_with_entropy(ref, case):
+    """compress(entropy=True) -> decompress: the decoded field equals the
+    oracle's decompression bit for bit, and the coded stream is smaller than
+    the raw codes would make it."""
+    import torch
+    if case == "sinusoid":
+        x = F.sinusoid_field((512, 512), seed=1)
+        args = (1e-4 * F.field_range(x), "abs", 16, "zero", 512)
+    elif case == "grf-rel":
+        x = F.power_law_grf((64, 64, 64), seed=2)
+        args = (1e-3, "rel", 8, "block_mean", 512)
+    else:
+        x = F.uniform_field((100000,), seed=5, lo=-10.0, hi=10.0)
+        args = (1e-3, "abs", 256, "zero", 64)
+    G.say(f"end to end with entropy: {case}")
+    s = dq.compress(torch.from_numpy(x).cuda(), *args, entropy=True)
+    assert s.codes is None and s.coded is not None
+    xh = dq.decompress(s).cpu().numpy()
+    p = ref.params(x.shape, *args)
+    c = ref.compress(p, x)
+    st, xr = ref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads)
+    assert st == 0 and s.n_out == c.n_out
+    assert np.array_equal(xh.view(np.uint32), xr.view(np.uint32))
+    raw = 2 * x.size + 8 * s.n_out + 4 * s.pads.numel() + 64
+    assert s.stream_bytes() < raw
