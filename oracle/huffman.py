@@ -19,7 +19,10 @@ implements, plainly:
   0, each next one (previous + 1) shifted left by the length difference;
 * the bitstream: chunks of CHUNK symbols, each starting on a 32-bit word,
   codewords concatenated most significant bit first; chunk_off[c] is the
-  first word of chunk c (chunk_off[n_chunks] = total words).
+  first word of chunk c (chunk_off[n_chunks] = total words); sub_off[c, k]
+  (k = 0, 1, 2) is the bit offset, from the start of chunk c, of its symbol
+  (k + 1) * SUB (the chunk's bit count when the chunk is shorter), so that a
+  chunk can be decoded from four places at once.
 """
 
 from __future__ import annotations
@@ -29,6 +32,7 @@ from collections import deque
 import numpy as np
 
 CHUNK = 1024
+SUB = 256
 MAX_LEN = 32
 
 
@@ -93,17 +97,24 @@ def canonical_codes(L):
     return C
 
 
-def encode(codes, L, C, chunk=CHUNK):
-    """Words (uint32) and chunk word offsets (uint64, n_chunks + 1)."""
+def encode(codes, L, C, chunk=CHUNK, with_sub=False):
+    """Words (uint32) and chunk word offsets (uint64, n_chunks + 1); with
+    with_sub also the sub-chunk bit offsets (uint16, n_chunks x 3)."""
     codes = np.asarray(codes, dtype=np.int64).ravel()
     n = codes.size
     nch = (n + chunk - 1) // chunk
-    words, off = [], [0]
+    words, off, sub = [], [0], []
     for c in range(nch):
         bits = []
-        for s in codes[c * chunk:(c + 1) * chunk]:
+        marks = []
+        for j, s in enumerate(codes[c * chunk:(c + 1) * chunk]):
+            if j and j % SUB == 0:
+                marks.append(len(bits))
             ln, cw = int(L[s]), int(C[s])
             bits.extend((cw >> (ln - 1 - k)) & 1 for k in range(ln))
+        while len(marks) < 3:
+            marks.append(len(bits))
+        sub.append(marks[:3])
         nw = (len(bits) + 31) // 32
         bits += [0] * (32 * nw - len(bits))
         for w in range(nw):
@@ -112,7 +123,10 @@ def encode(codes, L, C, chunk=CHUNK):
                 v = (v << 1) | b
             words.append(v)
         off.append(off[-1] + nw)
-    return np.array(words, dtype=np.uint32), np.array(off, dtype=np.uint64)
+    words, off = np.array(words, dtype=np.uint32), np.array(off, dtype=np.uint64)
+    if with_sub:
+        return words, off, np.array(sub, dtype=np.uint16).reshape(-1, 3)
+    return words, off
 
 
 def decode(words, off, n, L, C, chunk=CHUNK):

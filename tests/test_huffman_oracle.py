@@ -88,3 +88,17 @@ def test_single_symbol_and_round_trips():
         w, off = H.encode(codes, L, C, chunk=chunk)
         assert off[-1] == w.size and off.size == (n + chunk - 1) // chunk + 1
         assert np.array_equal(H.decode(w, off, n, L, C, chunk=chunk), codes)
+
+
+def test_sub_chunk_offsets():
+    """Sub-chunk offsets: the bits of the first 256 / 512 / 768 codewords of
+    each chunk, or the chunk's bit count for a shorter chunk."""
+    rng = np.random.default_rng(4)
+    codes = np.minimum(rng.geometric(0.1, size=2500) - 1, 63)
+    L = H.code_lengths(H.histogram(codes, 64))
+    C = H.canonical_codes(L)
+    w, off, sub = H.encode(codes, L, C, with_sub=True)
+    for c in range(sub.shape[0]):
+        part = codes[c * 1024:(c + 1) * 1024]
+        for k in range(3):
+            assert sub[c, k] == int(L[part[:256 * (k + 1)]].sum())
