@@ -280,7 +280,7 @@ def entropy_report(codecs, pads, n_out, reps=10):
         assert torch.equal(back, codes)
         words = int(bs.chunk_off[-1].item())
         nch = bs.chunk_off.numel() - 1
-        stream = 4 * words + 8 * (nch + 1) + K + 8 * n_out[pad] + 4 * dq.pad_count(cd.p) + 64
+        stream = 4 * words + 8 * (nch + 1) + 6 * nch + K + 8 * n_out[pad] + 4 * dq.pad_count(cd.p) + 64
         out[pad] = {"bits_per_code": round(32.0 * words / n, 4), "ratio_vs_fp32": round(4.0 * n / stream, 3),
                     "codebook_ms": round(t["codebook"], 4), "encode_ms": round(t["encode"], 4),
                     "decode_ms": round(t["decode"], 4),

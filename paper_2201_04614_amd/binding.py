@@ -217,7 +217,7 @@ class DQStream:
         if self.codes is not None:
             return b + 2 * self.codes.numel()
         c = self.coded
-        return b + 4 * c.words.numel() + 8 * c.chunk_off.numel() + c.lengths.numel()
+        return b + 4 * c.words.numel() + 8 * c.chunk_off.numel() + 2 * c.sub_off.numel() + c.lengths.numel()
 
 
 @dataclass
@@ -226,6 +226,7 @@ class HuffCoded:
     n_symbols: int
     lengths: object    # torch.uint8 [n_symbols]
     chunk_off: object  # torch.int64 [n_chunks + 1]
+    sub_off: object    # torch.int16 [n_chunks, 3]
     words: object      # torch.int32 [words]
 
 
@@ -346,7 +347,7 @@ def compress(x, eb, eb_mode="abs", block=16, pad="zero", radius=512, out_cap=Non
         if st != DQ_OK:
             raise DQError(st, "huffman encode")
         total = int(bs.chunk_off[-1].item())
-        s.coded = HuffCoded(2 * codec.radius, cb.lengths, bs.chunk_off, bs.words[:total].clone())
+        s.coded = HuffCoded(2 * codec.radius, cb.lengths, bs.chunk_off, bs.sub_off, bs.words[:total].clone())
         s.codes = None
     return s
 
@@ -360,7 +361,7 @@ def decompress(s: DQStream, out=None):
         from . import huffman as HF
         c = s.coded
         n = int(np.prod(s.shape))
-        bs = HF.Bitstream(n, c.chunk_off, c.words, None)
+        bs = HF.Bitstream(n, c.chunk_off, c.sub_off, c.words, None)
         flat, hst = HF.decode(bs, HF.Codebook(c.n_symbols, None, c.lengths, None, None))
         if int(hst.item()) != DQ_OK:
             raise DQError(int(hst.item()), "huffman decode")

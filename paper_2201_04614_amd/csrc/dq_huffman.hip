@@ -12,7 +12,8 @@
 //  k_huff_dtable      decode tables: counts / first codewords / first ranks per
 //                     length, symbols in (length, symbol) order, an 11-bit
 //                     lookup table
-//  k_huff_decode      one thread per chunk: 64-bit bit buffer in registers,
+//  k_huff_decode      four threads per chunk (from its sub-chunk offsets):
+//                     64-bit bit buffer in registers,
 //                     lookup table for codewords of at most 11 bits, canonical
 //                     search above
 #include "dq_device.hpp"
@@ -22,12 +23,13 @@ namespace dq {
 namespace {
 
 constexpr uint32_t kChunk = DQ_HUFF_CHUNK;
+constexpr uint32_t kSub = DQ_HUFF_SUB;  // a chunk is decoded from kChunk / kSub places
 constexpr uint32_t kMaxPresent = DQ_HUFF_MAX_PRESENT;
 constexpr int kMaxLen = 32;
 constexpr int kLutBits = 11;
 constexpr uint32_t kLocalBins = 8192;
 constexpr uint32_t kStage = 16;              // words a decoding thread stages at a time
-constexpr uint64_t kStageMinChunks = 65536;  // staging pays once the chunks fill the GPU
+constexpr uint64_t kStageMinThreads = 262144;  // staging pays once the decoding threads fill the GPU
 constexpr int ST_ENOTSUP = DQ_ENOTSUP;
 
 struct DTable {
@@ -341,7 +343,8 @@ __global__ __launch_bounds__(256) void k_huff_encode(const uint16_t* __restrict_
                                                      const uint8_t* __restrict__ lengths,
                                                      const uint32_t* __restrict__ codewords,
                                                      const unsigned long long* __restrict__ chunk_off,
-                                                     uint32_t* __restrict__ words, uint64_t cap) {
+                                                     uint32_t* __restrict__ words, uint64_t cap,
+                                                     uint16_t* __restrict__ sub_off) {
     __shared__ uint32_t buf[4][kChunk];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t c = (uint64_t)blockIdx.x * 4u + wave;
@@ -366,6 +369,13 @@ __global__ __launch_bounds__(256) void k_huff_encode(const uint16_t* __restrict_
     }
     const uint32_t incl = wave_scan_incl(bits, lane);
     uint32_t p = incl - bits;
+    // lane l holds codes 16 l ..: the bit offsets of codes 256, 512, 768
+    const uint32_t s1 = readlane(p, 16), s2 = readlane(p, 32), s3 = readlane(p, 48);
+    if (lane == 0) {
+        sub_off[c * 3 + 0] = (uint16_t)s1;
+        sub_off[c * 3 + 1] = (uint16_t)s2;
+        sub_off[c * 3 + 2] = (uint16_t)s3;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -472,6 +482,7 @@ __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict_
 // loads the next word one refill ahead in a register instead.
 __global__ __launch_bounds__(256) void k_huff_decode(const uint32_t* __restrict__ words, uint64_t n_words,
                                                      const unsigned long long* __restrict__ chunk_off, uint64_t n,
+                                                     const uint16_t* __restrict__ sub_off,
                                                      const DTable* __restrict__ t, uint16_t* __restrict__ out,
                                                      int32_t* status, int staged) {
     __shared__ uint32_t lut[1u << kLutBits];
@@ -487,18 +498,29 @@ __global__ __launch_bounds__(256) void k_huff_decode(const uint32_t* __restrict_
         fidx[threadIdx.x] = t->first_index[threadIdx.x];
     }
     __syncthreads();
-    const uint64_t c = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint64_t tg = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint64_t c = tg / (kChunk / kSub);                   // chunk
+    const uint32_t part = (uint32_t)(tg % (kChunk / kSub));    // its part
     const uint64_t nch = (n + kChunk - 1) / kChunk;
     if (c >= nch) return;
+    const uint32_t mc = (uint32_t)min((uint64_t)kChunk, n - c * kChunk);
+    if (part * kSub >= mc) return;
+    const uint32_t m = min(kSub, mc - part * kSub);
     const uint64_t wbeg = chunk_off[c];
     const uint64_t wend = min(chunk_off[c + 1], n_words);  // reads stay inside the words buffer
-    uint64_t w = wbeg;
-    uint64_t used = 0;
-    const uint32_t m = (uint32_t)min((uint64_t)kChunk, n - c * kChunk);
-    unsigned long long buf = 0;
-    int have = 0;
+    if (wend < wbeg) {
+        set_status(status, ST_ECORRUPT);
+        return;
+    }
+    const uint32_t start = part ? sub_off[c * 3 + part - 1] : 0u;  // bit offset in the chunk
+    uint64_t w = wbeg + (start >> 5);
+    uint64_t used = start;
     bool bad = false;
-    uint16_t* o = out + c * kChunk;
+    // the first word, its leading bits skipped
+    unsigned long long buf = (unsigned long long)(w < wend ? words[w] : 0u) << (32 + (start & 31u));
+    int have = 32 - (int)(start & 31u);
+    ++w;
+    uint16_t* o = out + c * kChunk + part * kSub;
     uint32_t* sb = stage[threadIdx.x];
     uint32_t sidx = kStage;
     uint32_t pre = 0;
@@ -547,7 +569,7 @@ __global__ __launch_bounds__(256) void k_huff_decode(const uint32_t* __restrict_
         have -= (int)len;
         used += len;
     }
-    if (bad || wend < wbeg || used > (wend - wbeg) * 32ull) set_status(status, ST_ECORRUPT);
+    if (bad || used > (wend - wbeg) * 32ull) set_status(status, ST_ECORRUPT);
 }
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
@@ -608,9 +630,9 @@ dq_status dq_huff_codebook(const uint16_t* codes, uint64_t n, uint32_t n_symbols
 }
 
 dq_status dq_huff_encode(const uint16_t* codes, uint64_t n, uint32_t n_symbols, const uint8_t* lengths,
-                         const uint32_t* codewords, uint64_t* chunk_off, uint32_t* words, uint64_t words_cap,
-                         int32_t* status, void* ws, uint64_t ws_bytes, void* hip_stream) {
-    if (!codes || !lengths || !codewords || !chunk_off || !words || !status || !ws) return DQ_EINVAL;
+                         const uint32_t* codewords, uint64_t* chunk_off, uint16_t* sub_off, uint32_t* words,
+                         uint64_t words_cap, int32_t* status, void* ws, uint64_t ws_bytes, void* hip_stream) {
+    if (!codes || !lengths || !codewords || !chunk_off || !sub_off || !words || !status || !ws) return DQ_EINVAL;
     if (n == 0 || n > 0xffffffffull || n_symbols < 1 || n_symbols > DQ_HUFF_MAX_SYMBOLS) return DQ_EINVAL;
     const Layout L = layout(n);
     if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) % 256) != 0) return DQ_EINVAL;
@@ -629,14 +651,14 @@ dq_status dq_huff_encode(const uint16_t* codes, uint64_t n, uint32_t n_symbols, 
     hipLaunchKernelGGL(k_huff_scan_c, dim3((uint32_t)nb), dim3(1024), 0, st, off, nch,
                        (const unsigned long long*)tot, (uint32_t)nb, words_cap, status);
     hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)((nch + 3) / 4)), dim3(256), 0, st, codes, n, n_symbols,
-                       lengths, codewords, (const unsigned long long*)off, words, words_cap);
+                       lengths, codewords, (const unsigned long long*)off, words, words_cap, sub_off);
     return launched();
 }
 
-dq_status dq_huff_decode(const uint32_t* words, uint64_t n_words, const uint64_t* chunk_off, uint64_t n,
-                         uint32_t n_symbols, const uint8_t* lengths, uint16_t* codes, int32_t* status, void* ws,
-                         uint64_t ws_bytes, void* hip_stream) {
-    if (!words || !chunk_off || !lengths || !codes || !status || !ws) return DQ_EINVAL;
+dq_status dq_huff_decode(const uint32_t* words, uint64_t n_words, const uint64_t* chunk_off,
+                         const uint16_t* sub_off, uint64_t n, uint32_t n_symbols, const uint8_t* lengths,
+                         uint16_t* codes, int32_t* status, void* ws, uint64_t ws_bytes, void* hip_stream) {
+    if (!words || !chunk_off || !sub_off || !lengths || !codes || !status || !ws) return DQ_EINVAL;
     if (n == 0 || n > 0xffffffffull || n_symbols < 1 || n_symbols > DQ_HUFF_MAX_SYMBOLS) return DQ_EINVAL;
     const Layout L = layout(n);
     if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) % 256) != 0) return DQ_EINVAL;
@@ -645,9 +667,10 @@ dq_status dq_huff_decode(const uint32_t* words, uint64_t n_words, const uint64_t
     const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     hipLaunchKernelGGL(k_huff_status_ok, dim3(1), dim3(64), 0, st, status);
     hipLaunchKernelGGL(k_huff_dtable, dim3(1), dim3(1024), 0, st, lengths, n_symbols, t, status);
-    hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)((nch + 255) / 256)), dim3(256), 0, st, words, n_words,
-                       reinterpret_cast<const unsigned long long*>(chunk_off), n, (const DTable*)t, codes, status,
-                       nch >= kStageMinChunks ? 1 : 0);
+    const uint64_t threads = nch * (kChunk / kSub);
+    hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st, words, n_words,
+                       reinterpret_cast<const unsigned long long*>(chunk_off), n, sub_off, (const DTable*)t, codes,
+                       status, threads >= kStageMinThreads ? 1 : 0);
     return launched();
 }
 

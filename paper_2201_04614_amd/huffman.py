@@ -31,8 +31,8 @@ def lib():
             "dq_huff_workspace": ([u64, pu64], C.c_int),
             "dq_huff_max_words": ([u64, pu64], C.c_int),
             "dq_huff_codebook": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, vp], C.c_int),
-            "dq_huff_encode": ([vp, u64, u32, vp, vp, vp, vp, u64, vp, vp, u64, vp], C.c_int),
-            "dq_huff_decode": ([vp, u64, vp, u64, u32, vp, vp, vp, vp, u64, vp], C.c_int),
+            "dq_huff_encode": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, vp, vp, u64, vp], C.c_int),
+            "dq_huff_decode": ([vp, u64, vp, vp, u64, u32, vp, vp, vp, vp, u64, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -82,6 +82,7 @@ class Codebook:
 class Bitstream:
     n: int
     chunk_off: object  # int64 [n_chunks + 1] (uint64 word offsets)
+    sub_off: object    # int16 [n_chunks, 3] (uint16 bit offsets of codes 256, 512, 768 in each chunk)
     words: object      # int32 [capacity] (uint32 words)
     status: object
 
@@ -108,12 +109,13 @@ def encode(codes, cb, ws=None, words_cap=None, stream=None):
         words_cap = int(w.value)
     nch = (n + CHUNK - 1) // CHUNK
     bs = Bitstream(n, torch.empty(nch + 1, dtype=torch.int64, device=dev),
+                   torch.empty((nch, 3), dtype=torch.int16, device=dev),
                    torch.empty(max(1, words_cap), dtype=torch.int32, device=dev),
                    torch.zeros(1, dtype=torch.int32, device=dev))
     wsb, nb = _aligned(ws if ws is not None else _ws(n, dev))
     _check(lib().dq_huff_encode(_p(codes), n, cb.n_symbols, _p(cb.lengths), _p(cb.codewords), _p(bs.chunk_off),
-                                _p(bs.words), int(words_cap), _p(bs.status), _p(wsb), nb, _s(stream)),
-           "dq_huff_encode")
+                                _p(bs.sub_off), _p(bs.words), int(words_cap), _p(bs.status), _p(wsb), nb,
+                                _s(stream)), "dq_huff_encode")
     return bs
 
 
@@ -124,6 +126,6 @@ def decode(bs, cb, out=None, ws=None, n_words=None, stream=None):
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     wsb, nb = _aligned(ws if ws is not None else _ws(bs.n, dev))
     nw = bs.words.numel() if n_words is None else int(n_words)
-    _check(lib().dq_huff_decode(_p(bs.words), nw, _p(bs.chunk_off), bs.n, cb.n_symbols, _p(cb.lengths), _p(out),
-                                _p(status), _p(wsb), nb, _s(stream)), "dq_huff_decode")
+    _check(lib().dq_huff_decode(_p(bs.words), nw, _p(bs.chunk_off), _p(bs.sub_off), bs.n, cb.n_symbols,
+                                _p(cb.lengths), _p(out), _p(status), _p(wsb), nb, _s(stream)), "dq_huff_decode")
     return out, status

@@ -53,9 +53,10 @@ def test_codebook_and_bitstream_bit_exact(case):
     cb, L, Cw = _check_codebook(codes, K)
     cd = _dev(codes)
     bs = HF.encode(cd, cb)
-    words, off = H.encode(codes, L, Cw)
+    words, off, sub = H.encode(codes, L, Cw, with_sub=True)
     assert int(bs.status.item()) == 0
     assert np.array_equal(bs.chunk_off.cpu().numpy().view(np.uint64), off)
+    assert np.array_equal(bs.sub_off.cpu().numpy().view(np.uint16), sub)
     assert np.array_equal(bs.words[:words.size].cpu().numpy().view(np.uint32), words)
     back, st = HF.decode(bs, cb)
     assert int(st.item()) == 0
