@@ -141,6 +141,7 @@ __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict_
     __shared__ unsigned long long key[kMaxPresent];
     __shared__ unsigned long long wint[kMaxPresent];  // internal weights, then depths
     __shared__ int16_t par_leaf[kMaxPresent], par_int[kMaxPresent];
+    __shared__ uint8_t len_sorted[kMaxPresent], len_sym[kMaxPresent];  // by sorted position / by psym position
     __shared__ uint32_t wsum[16];
     __shared__ int too_long;
     const int tid = threadIdx.x;
@@ -224,14 +225,26 @@ __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict_
         if (!too_long) break;
         __syncthreads();
     }
-    if (tid == 0) {
+    for (uint32_t i = tid; i < np; i += 1024u) len_sorted[i] = (uint8_t)(wint[par_leaf[i]] + 1);
+    __syncthreads();
+    // lengths by symbol: out to memory, and in LDS by the symbol's place in psym
+    // (psym is in symbol order: a binary search finds it)
+    for (uint32_t i = tid; i < np; i += 1024u) {
+        const uint32_t s = (uint32_t)(key[i] & 0xffffu);
+        lengths[s] = len_sorted[i];
+        uint32_t lo = 0, hi = np;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (psym[mid] < s) lo = mid + 1;
+            else hi = mid;
+        }
+        len_sym[lo] = len_sorted[i];
+    }
+    __syncthreads();
+    if (tid == 0) {  // canonical codewords: within a length in symbol order (LDS reads only)
         uint32_t bl_count[kMaxLen + 1];
         for (int l = 0; l <= kMaxLen; ++l) bl_count[l] = 0;
-        for (uint32_t i = 0; i < np; ++i) {
-            const int L = (int)wint[par_leaf[i]] + 1;
-            lengths[key[i] & 0xffffu] = (uint8_t)L;
-            ++bl_count[L];
-        }
+        for (uint32_t i = 0; i < np; ++i) ++bl_count[len_sym[i]];
         unsigned long long next[kMaxLen + 1];
         unsigned long long code = 0;
         next[0] = 0;
@@ -239,12 +252,7 @@ __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict_
             code = (code + (l > 1 ? bl_count[l - 1] : 0u)) << 1;
             next[l] = code;
         }
-        // codewords in symbol order within each length (the thread reads its own writes)
-        for (uint32_t i = 0; i < np; ++i) {
-            const uint32_t s = psym[i];
-            const int L = lengths[s];
-            codewords[s] = (uint32_t)next[L]++;
-        }
+        for (uint32_t i = 0; i < np; ++i) codewords[psym[i]] = (uint32_t)next[len_sym[i]]++;
     }
 }
 
@@ -402,10 +410,15 @@ __global__ __launch_bounds__(256) void k_huff_encode(const uint16_t* __restrict_
 __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict__ lengths, uint32_t K,
                                                       DTable* __restrict__ t, int32_t* status) {
     __shared__ uint16_t psym[kMaxPresent];
+    __shared__ uint16_t sorted[kMaxPresent];
+    __shared__ uint8_t lenp[kMaxPresent];
+    __shared__ uint32_t lut[1u << kLutBits];
+    __shared__ uint32_t cnt[kMaxLen + 1], fcode[kMaxLen + 1], fidx[kMaxLen + 1];
     __shared__ uint32_t wsum[16];
+    __shared__ int bad;
     const int tid = threadIdx.x;
-    // present symbols: lengths > 0 (compaction in symbol order)
     const int lane = tid & 63, wave = tid >> 6;
+    // present symbols: lengths > 0 (compaction in symbol order)
     uint32_t total = 0;
     for (uint32_t base = 0; base < K; base += 1024u) {
         const uint32_t s = base + (uint32_t)tid;
@@ -423,55 +436,67 @@ __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict_
         total += all;
         __syncthreads();
     }
-    for (uint32_t i = tid; i < (1u << kLutBits); i += 1024u) t->lut[i] = 0u;
     if (total > kMaxPresent) {
-        if (tid == 0) set_status(status, ST_ENOTSUP);
+        for (uint32_t i = tid; i < (1u << kLutBits); i += 1024u) t->lut[i] = 0u;
+        if (tid == 0) {
+            t->n_present = 0;
+            set_status(status, ST_ENOTSUP);
+        }
         return;
     }
+    for (uint32_t i = tid; i < total; i += 1024u) lenp[i] = lengths[psym[i]];
+    for (uint32_t i = tid; i < (1u << kLutBits); i += 1024u) lut[i] = 0u;
+    if (tid == 0) bad = 0;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t count[kMaxLen + 1];
+    if (tid == 0) {  // per-length counts, first codewords and ranks; symbols in (length, symbol) order
+        uint32_t count[kMaxLen + 1], fill[kMaxLen + 1];
         for (int l = 0; l <= kMaxLen; ++l) count[l] = 0;
-        bool bad = false;
         for (uint32_t i = 0; i < total; ++i) {
-            const uint32_t l = lengths[psym[i]];
-            if (l > (uint32_t)kMaxLen) {
-                bad = true;
-            } else {
-                ++count[l];
-            }
+            const uint32_t l = lenp[i];
+            if (l > (uint32_t)kMaxLen) bad = 1;
+            else ++count[l];
         }
         unsigned long long code = 0;
         uint32_t idx = 0;
-        uint32_t fill[kMaxLen + 1];
         for (int l = 0; l <= kMaxLen; ++l) {
             if (l > 0) code = (code + (l > 1 ? count[l - 1] : 0u)) << 1;
-            t->count[l] = l > 0 ? count[l] : 0u;
-            t->first_code[l] = (uint32_t)code;
-            t->first_index[l] = idx;
+            cnt[l] = l > 0 ? count[l] : 0u;
+            fcode[l] = (uint32_t)code;
+            fidx[l] = idx;
             fill[l] = idx;
             idx += l > 0 ? count[l] : 0u;
         }
-        for (uint32_t i = 0; i < total; ++i) {  // (length, symbol) order
-            const uint32_t s = psym[i];
-            const uint32_t l = lengths[s];
-            if (l <= (uint32_t)kMaxLen) t->sorted[fill[l]++] = (uint16_t)s;
+        for (uint32_t i = 0; i < total; ++i) {
+            const uint32_t l = lenp[i];
+            if (l <= (uint32_t)kMaxLen) sorted[fill[l]++] = psym[i];
         }
+    }
+    __syncthreads();
+    // lookup table: the codeword at sorted position j (length l <= kLutBits)
+    // covers 2^(kLutBits - l) entries; lengths that break the prefix
+    // property could reach past the table
+    for (uint32_t j = tid; j < total; j += 1024u) {
+        uint32_t l = 1;
+        while (l <= (uint32_t)kLutBits && !(j >= fidx[l] && j < fidx[l] + cnt[l])) ++l;
+        if (l > (uint32_t)kLutBits) continue;
+        const unsigned long long cw = (unsigned long long)fcode[l] + (j - fidx[l]);
+        const unsigned long long lo = cw << (kLutBits - l), hi = (cw + 1ull) << (kLutBits - l);
+        if (hi > (1ull << kLutBits)) {
+            bad = 1;
+            continue;
+        }
+        for (unsigned long long e = lo; e < hi; ++e) lut[e] = ((uint32_t)sorted[j] << 8) | l;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < (1u << kLutBits); i += 1024u) t->lut[i] = lut[i];
+    for (uint32_t i = tid; i < total; i += 1024u) t->sorted[i] = sorted[i];
+    if (tid <= kMaxLen) {
+        t->count[tid] = cnt[tid];
+        t->first_code[tid] = fcode[tid];
+        t->first_index[tid] = fidx[tid];
+    }
+    if (tid == 0) {
         t->n_present = total;
-        // lookup table: a codeword of length l <= kLutBits covers 2^(kLutBits - l)
-        // entries; lengths that break the prefix property could reach past it
-        for (int l = 1; l <= kLutBits; ++l) {
-            for (uint32_t r = 0; r < t->count[l]; ++r) {
-                const uint32_t s = t->sorted[t->first_index[l] + r];
-                const unsigned long long cw = (unsigned long long)t->first_code[l] + r;
-                const unsigned long long lo = cw << (kLutBits - l), hi = (cw + 1ull) << (kLutBits - l);
-                if (hi > (1ull << kLutBits)) {
-                    bad = true;
-                    break;
-                }
-                for (unsigned long long e = lo; e < hi; ++e) t->lut[e] = (s << 8) | (uint32_t)l;
-            }
-        }
         if (bad) set_status(status, ST_EINVAL);
     }
 }
