@@ -134,6 +134,64 @@ __device__ uint32_t compact_present(const uint32_t* __restrict__ hist, uint32_t 
     return total;
 }
 
+// Ascending bitonic sort of keys[0 .. P) in LDS (P a power of two), by a
+// workgroup of 1024 threads.
+__device__ void bitonic_sort_lds(unsigned long long* keys, uint32_t P) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < P; i += 1024u) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = keys[i], b = keys[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        keys[i] = b;
+                        keys[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Canonical order of the n present symbols psym[i] with lengths len[i]
+// (both in LDS): keys sorted by (length, symbol), the count of each length,
+// its first codeword and its first sorted position. Lengths above kMaxLen
+// sort last and are not counted (bad = 1). Workgroup of 1024 threads.
+__device__ void canonical_order(const uint8_t* len, const uint16_t* psym, uint32_t n, unsigned long long* keys,
+                                uint32_t* cnt, uint32_t* fcode, uint32_t* fidx, int* bad) {
+    const uint32_t tid = threadIdx.x;
+    if (tid <= (uint32_t)kMaxLen) cnt[tid] = 0u;
+    __syncthreads();
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    for (uint32_t i = tid; i < P; i += 1024u) {
+        if (i < n) {
+            const uint32_t l = len[i];
+            keys[i] = ((unsigned long long)l << 16) | psym[i];
+            if (l > (uint32_t)kMaxLen) *bad = 1;
+            else atomicAdd(&cnt[l], 1u);
+        } else {
+            keys[i] = ~0ull;
+        }
+    }
+    __syncthreads();
+    bitonic_sort_lds(keys, P);
+    if (tid == 0) {
+        unsigned long long code = 0;
+        uint32_t idx = 0;
+        for (int l = 0; l <= kMaxLen; ++l) {
+            if (l > 0) code = (code + (l > 1 ? cnt[l - 1] : 0u)) << 1;
+            fcode[l] = (uint32_t)code;
+            fidx[l] = idx;
+            idx += l > 0 ? cnt[l] : 0u;
+        }
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict__ hist, uint32_t K,
                                                      uint8_t* __restrict__ lengths,
                                                      uint32_t* __restrict__ codewords, int32_t* status) {
@@ -143,7 +201,8 @@ __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict_
     __shared__ int16_t par_leaf[kMaxPresent], par_int[kMaxPresent];
     __shared__ uint8_t len_sorted[kMaxPresent], len_sym[kMaxPresent];  // by sorted position / by psym position
     __shared__ uint32_t wsum[16];
-    __shared__ int too_long;
+    __shared__ uint32_t cnt[kMaxLen + 1], fcode[kMaxLen + 1], fidx[kMaxLen + 1];
+    __shared__ int too_long, bad;
     const int tid = threadIdx.x;
     for (uint32_t s = tid; s < K; s += 1024u) {
         lengths[s] = 0;
@@ -178,22 +237,7 @@ __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict_
             }
         }
         __syncthreads();
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < P; i += 1024u) {
-                    const uint32_t l = i ^ j;
-                    if (l > i) {
-                        const unsigned long long a = key[i], b = key[l];
-                        const bool up = (i & k) == 0;
-                        if ((a > b) == up) {
-                            key[i] = b;
-                            key[l] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        bitonic_sort_lds(key, P);
         if (tid == 0) {
             // two queues: leaves in key order, internal nodes in creation order;
             // the lighter front first, a leaf on equal weights
@@ -240,19 +284,14 @@ __global__ __launch_bounds__(1024) void k_huff_build(const uint32_t* __restrict_
         }
         len_sym[lo] = len_sorted[i];
     }
+    if (tid == 0) bad = 0;
     __syncthreads();
-    if (tid == 0) {  // canonical codewords: within a length in symbol order (LDS reads only)
-        uint32_t bl_count[kMaxLen + 1];
-        for (int l = 0; l <= kMaxLen; ++l) bl_count[l] = 0;
-        for (uint32_t i = 0; i < np; ++i) ++bl_count[len_sym[i]];
-        unsigned long long next[kMaxLen + 1];
-        unsigned long long code = 0;
-        next[0] = 0;
-        for (int l = 1; l <= kMaxLen; ++l) {
-            code = (code + (l > 1 ? bl_count[l - 1] : 0u)) << 1;
-            next[l] = code;
-        }
-        for (uint32_t i = 0; i < np; ++i) codewords[psym[i]] = (uint32_t)next[len_sym[i]]++;
+    // canonical codewords: symbols in (length, symbol) order get consecutive
+    // codewords from their length's first one
+    canonical_order(len_sym, psym, np, key, cnt, fcode, fidx, &bad);
+    for (uint32_t j = tid; j < np; j += 1024u) {
+        const uint32_t l = (uint32_t)(key[j] >> 16);
+        codewords[key[j] & 0xffffu] = fcode[l] + (j - fidx[l]);
     }
 }
 
@@ -412,6 +451,7 @@ __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict_
     __shared__ uint16_t psym[kMaxPresent];
     __shared__ uint16_t sorted[kMaxPresent];
     __shared__ uint8_t lenp[kMaxPresent];
+    __shared__ unsigned long long keys[kMaxPresent];
     __shared__ uint32_t lut[1u << kLutBits];
     __shared__ uint32_t cnt[kMaxLen + 1], fcode[kMaxLen + 1], fidx[kMaxLen + 1];
     __shared__ uint32_t wsum[16];
@@ -448,36 +488,14 @@ __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict_
     for (uint32_t i = tid; i < (1u << kLutBits); i += 1024u) lut[i] = 0u;
     if (tid == 0) bad = 0;
     __syncthreads();
-    if (tid == 0) {  // per-length counts, first codewords and ranks; symbols in (length, symbol) order
-        uint32_t count[kMaxLen + 1], fill[kMaxLen + 1];
-        for (int l = 0; l <= kMaxLen; ++l) count[l] = 0;
-        for (uint32_t i = 0; i < total; ++i) {
-            const uint32_t l = lenp[i];
-            if (l > (uint32_t)kMaxLen) bad = 1;
-            else ++count[l];
-        }
-        unsigned long long code = 0;
-        uint32_t idx = 0;
-        for (int l = 0; l <= kMaxLen; ++l) {
-            if (l > 0) code = (code + (l > 1 ? count[l - 1] : 0u)) << 1;
-            cnt[l] = l > 0 ? count[l] : 0u;
-            fcode[l] = (uint32_t)code;
-            fidx[l] = idx;
-            fill[l] = idx;
-            idx += l > 0 ? count[l] : 0u;
-        }
-        for (uint32_t i = 0; i < total; ++i) {
-            const uint32_t l = lenp[i];
-            if (l <= (uint32_t)kMaxLen) sorted[fill[l]++] = psym[i];
-        }
-    }
-    __syncthreads();
-    // lookup table: the codeword at sorted position j (length l <= kLutBits)
-    // covers 2^(kLutBits - l) entries; lengths that break the prefix
-    // property could reach past the table
+    canonical_order(lenp, psym, total, keys, cnt, fcode, fidx, &bad);
+    // symbols in (length, symbol) order, and the lookup table: the codeword at
+    // sorted position j (length l <= kLutBits) covers 2^(kLutBits - l)
+    // entries; lengths that break the prefix property could reach past it
     for (uint32_t j = tid; j < total; j += 1024u) {
-        uint32_t l = 1;
-        while (l <= (uint32_t)kLutBits && !(j >= fidx[l] && j < fidx[l] + cnt[l])) ++l;
+        const uint32_t l = (uint32_t)(keys[j] >> 16);
+        const uint32_t sym = (uint32_t)(keys[j] & 0xffffu);
+        sorted[j] = (uint16_t)sym;
         if (l > (uint32_t)kLutBits) continue;
         const unsigned long long cw = (unsigned long long)fcode[l] + (j - fidx[l]);
         const unsigned long long lo = cw << (kLutBits - l), hi = (cw + 1ull) << (kLutBits - l);
@@ -485,7 +503,7 @@ __global__ __launch_bounds__(1024) void k_huff_dtable(const uint8_t* __restrict_
             bad = 1;
             continue;
         }
-        for (unsigned long long e = lo; e < hi; ++e) lut[e] = ((uint32_t)sorted[j] << 8) | l;
+        for (unsigned long long e = lo; e < hi; ++e) lut[e] = (sym << 8) | l;
     }
     __syncthreads();
     for (uint32_t i = tid; i < (1u << kLutBits); i += 1024u) t->lut[i] = lut[i];
