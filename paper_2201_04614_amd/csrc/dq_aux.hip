@@ -425,20 +425,48 @@ void launch_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out
 
 // ------------------------------------------------------------------ decompress
 
-struct IndexGeom {
-    Geom g;
-    uint32_t lb;   // log2 B
-    uint32_t dim;
+// Unsigned 32-bit division by a divisor fixed for the launch: a multiply-high
+// and two shifts (the round-up method of Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994). With l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1 (which fits in 32 bits),
+//     n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0),  t = mulhi(m, n),
+// exactly, for every 32-bit n.
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+    __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        const uint32_t t = __umulhi(m, n);
+        return (t + ((n - t) >> s1)) >> s2;
+    }
 };
 
-__device__ __forceinline__ void cell_block(const IndexGeom& ig, uint32_t idx, uint32_t& bid, uint32_t& local) {
-    const uint32_t x = idx % ig.g.nx;
-    const uint32_t rest = idx / ig.g.nx;
-    const uint32_t y = rest % ig.g.ny;
-    const uint32_t z = rest / ig.g.ny;
-    bid = ((z >> ig.lb) * ig.g.nby + (y >> ig.lb)) * ig.g.nbx + (x >> ig.lb);
+static FastDiv make_fastdiv(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < (unsigned long long)d) ++l;
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)((((unsigned __int128)1 << 32) * ((1ull << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1u;
+    f.s2 = l > 1 ? l - 1 : 0u;
+    return f;
+}
+
+struct IndexGeom {
+    Geom g;
+    FastDiv dx, dy;  // by nx, by ny
+    uint32_t lb;     // log2 B
+};
+
+// (block, local row-major position) of a cell as one 64-bit key: the list's
+// order is the keys' order.
+__device__ __forceinline__ uint64_t cell_key(const IndexGeom& ig, uint32_t idx) {
+    const uint32_t rest = ig.dx.div(idx);
+    const uint32_t x = idx - rest * ig.g.nx;
+    const uint32_t z = ig.dy.div(rest);
+    const uint32_t y = rest - z * ig.g.ny;
+    const uint32_t bid = ((z >> ig.lb) * ig.g.nby + (y >> ig.lb)) * ig.g.nbx + (x >> ig.lb);
     const uint32_t m = (1u << ig.lb) - 1u;
-    local = (((z & m) << ig.lb | (y & m)) << ig.lb) | (x & m);
+    const uint32_t local = (((z & m) << ig.lb | (y & m)) << ig.lb) | (x & m);
+    return ((uint64_t)bid << 32) | local;
 }
 
 // First position in [lo, hi) of the outlier list whose block is >= b (hi if
@@ -448,65 +476,93 @@ __device__ __forceinline__ uint32_t first_at_or_after(const uint32_t* __restrict
     while (lo < hi) {
         const uint32_t mid = lo + (hi - lo) / 2;
         const uint32_t idx = out_idx[mid];
-        uint32_t bb = 0xffffffffu, l;
-        if (idx < ig.g.N) cell_block(ig, idx, bb, l);
+        const uint32_t bb = idx < ig.g.N ? (uint32_t)(cell_key(ig, idx) >> 32) : 0xffffffffu;
         if (bb < b) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
+constexpr uint32_t kIndexGrid = 4096;  // workgroups at most; both loops stride over the grid
+constexpr int kIndexUnroll = 4;        // list entries per lane per step (loads in flight together)
+
 // block_start[b] = first outlier of block b or later (b = 0..n_blocks);
-// outliers must be in strictly increasing (block, local row-major) order.
+// outliers must be in strictly increasing (block, local row-major) order,
+// else the call's status becomes DQ_ECORRUPT.
 __global__ __launch_bounds__(256) void k_index(const uint32_t* __restrict__ out_idx, uint32_t n_out,
                                                IndexGeom ig, uint32_t* __restrict__ block_start,
                                                unsigned long long* res_word, uint32_t tag,
                                                const ResultView* src, uint32_t cap) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const uint64_t N = ig.g.N;
     if (src) {  // the count of the compress call that wrote the list (at most its capacity)
         const unsigned long long n = src->n_out;
         n_out = (uint32_t)(n < cap ? n : cap);
     }
-    if (i < n_out) {
-        const uint32_t idx = out_idx[i];
-        bool ok = idx < N;
-        if (ok && i > 0) {
-            const uint32_t prev = out_idx[i - 1];
-            if (prev >= N) {
-                ok = false;
-            } else {
-                uint32_t b0, l0, b1, l1;
-                cell_block(ig, prev, b0, l0);
-                cell_block(ig, idx, b1, l1);
-                ok = (b0 < b1) || (b0 == b1 && l0 < l1);
-            }
+    // order check: each wave takes kIndexUnroll x 64 consecutive entries per
+    // step; an entry's predecessor key comes from the lane below, lane 0 of a
+    // piece takes lane 63 of the piece before, the wave's first entry loads
+    // its predecessor. A key of ~0 marks an index outside the field.
+    constexpr uint64_t kBad = ~0ull;
+    const uint32_t wave_step = kIndexUnroll * 64u;
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    bool bad = false;
+    for (uint64_t base = (uint64_t)wave_id * wave_step; base < n_out; base += (uint64_t)n_waves * wave_step) {
+        uint32_t idx[kIndexUnroll];
+#pragma unroll
+        for (int u = 0; u < kIndexUnroll; ++u) {
+            const uint64_t i = base + (uint64_t)u * 64u + (uint64_t)lane;
+            idx[u] = i < n_out ? out_idx[i] : 0u;
         }
-        if (!ok) status_corrupt_tagged(res_word, tag);
+        uint32_t before = 0;
+        if (lane == 0 && base > 0) before = out_idx[base - 1];
+        uint64_t carry = (base > 0 && before < N) ? cell_key(ig, before) : kBad;
+#pragma unroll
+        for (int u = 0; u < kIndexUnroll; ++u) {
+            const uint64_t i = base + (uint64_t)u * 64u + (uint64_t)lane;
+            const bool in = i < n_out;
+            const uint64_t key = (in && idx[u] < N) ? cell_key(ig, idx[u]) : kBad;
+            const uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+            uint64_t prev = ((uint64_t)(uint32_t)__shfl_up((int)hi, 1) << 32) | (uint32_t)__shfl_up((int)lo, 1);
+            if (lane == 0) prev = carry;
+            if (in) bad |= key == kBad || (i > 0 && !(prev < key));
+            carry = ((uint64_t)readlane(hi, 63) << 32) | readlane(lo, 63);
+        }
     }
-    // block_start of the workgroup's 256 blocks: two searches over the whole
+    if (bad) status_corrupt_tagged(res_word, tag);
+    // block_start of 256 blocks per workgroup step: two searches over the
     // list bound the range in which all of them lie, then every thread
     // searches that (short, cache-resident) range
     __shared__ uint32_t range[2];
-    const uint32_t b0 = blockIdx.x * blockDim.x;
-    if (b0 <= ig.g.nblocks) {  // uniform in the workgroup
+    const uint32_t nb1 = ig.g.nblocks + 1;
+    uint32_t from = 0;
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < nb1; b0 += gridDim.x * blockDim.x) {  // uniform in the workgroup
         if (threadIdx.x < 2) {
-            const uint32_t target = threadIdx.x == 0 ? b0 : min(b0 + blockDim.x, ig.g.nblocks + 1);
-            range[threadIdx.x] = first_at_or_after(out_idx, 0, n_out, target, ig);
+            const uint32_t target = threadIdx.x == 0 ? b0 : min(b0 + blockDim.x, nb1);
+            range[threadIdx.x] = first_at_or_after(out_idx, from, n_out, target, ig);
         }
         __syncthreads();
-        if (i <= ig.g.nblocks) block_start[i] = first_at_or_after(out_idx, range[0], range[1], i, ig);
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t r0 = range[0], r1 = range[1];
+        if (b < nb1) block_start[b] = first_at_or_after(out_idx, r0, r1, b, ig);
+        from = r1;  // later steps look at later blocks
+        __syncthreads();
     }
 }
 
 void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log2, int dim,
                   uint32_t* block_start, void* res, uint32_t tag, hipStream_t stream, const void* src,
                   uint32_t cap) {
-    IndexGeom ig{g, (uint32_t)block_log2, (uint32_t)dim};
+    (void)dim;
+    IndexGeom ig{g, make_fastdiv(g.nx), make_fastdiv(g.ny), (uint32_t)block_log2};
     const uint64_t cnt = src ? (uint64_t)cap : (uint64_t)n_out;  // with src: the largest possible count
-    const uint64_t work = cnt > (uint64_t)g.nblocks + 1 ? cnt : (uint64_t)g.nblocks + 1;
-    const uint32_t blocks = (uint32_t)((work + 255) / 256);
-    hipLaunchKernelGGL(k_index, dim3(blocks), dim3(256), 0, stream, out_idx, n_out, ig, block_start,
+    const uint64_t list_groups = (cnt + 4u * kIndexUnroll * 64u - 1) / (4u * kIndexUnroll * 64u);
+    const uint64_t block_groups = ((uint64_t)g.nblocks + 1 + 255) / 256;
+    uint64_t blocks = list_groups > block_groups ? list_groups : block_groups;
+    if (blocks > kIndexGrid) blocks = kIndexGrid;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_index, dim3((uint32_t)blocks), dim3(256), 0, stream, out_idx, n_out, ig, block_start,
                        reinterpret_cast<unsigned long long*>(res), tag, (const ResultView*)src, cap);
 }
 
