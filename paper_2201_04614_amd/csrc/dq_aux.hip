@@ -99,12 +99,12 @@ __global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restri
         const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
         uint64_t i = tid;
         for (; i + stride < n4; i += 2 * stride) {  // two 16-byte loads in flight
-            const f32x4 v0 = __builtin_nontemporal_load(x4 + i);
-            const f32x4 v1 = __builtin_nontemporal_load(x4 + i + stride);
+            const f32x4 v0 = x4[i];
+            const f32x4 v1 = x4[i + stride];
             minmax_acc4(v0, mn, mx, nfa);
             minmax_acc4(v1, mn, mx, nfa);
         }
-        for (; i < n4; i += stride) minmax_acc4(__builtin_nontemporal_load(x4 + i), mn, mx, nfa);
+        for (; i < n4; i += stride) minmax_acc4(x4[i], mn, mx, nfa);
         start = n4 * 4;
     }
     for (uint64_t i = start + tid; i < N; i += stride) minmax_acc(x[i], mn, mx, nfa);

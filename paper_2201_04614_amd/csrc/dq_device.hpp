@@ -345,6 +345,7 @@ __device__ __forceinline__ uint32_t edge_effective(const int32_t* e) {
 // lane needs it.
 constexpr double kNearHalf = 0.5 - 1.52587890625e-05;  // 0.5 - 2^-16
 constexpr double kQMax = 2147483647.0;
+constexpr double kRoundShift = 6755399441055744.0;  // 1.5 * 2^52
 
 __device__ __forceinline__ double exact_round(float x, double k, double twoeb, double eb) {
     const double e = __builtin_fma(-twoeb, k, (double)x);

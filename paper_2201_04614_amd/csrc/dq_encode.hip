@@ -111,23 +111,28 @@ __device__ __forceinline__ void stage_row_outliers(const EncArgs& a, uint32_t& r
 template <int V, int NR>
 __device__ __forceinline__ void prequant_rows(const float (&xv)[NR][V], double r, double twoeb, double eb,
                                               uint32_t (&q)[NR][V], uint64_t& bad) {
-    // near-half test per value, as a ballot mask (false for NaN, so a
-    // non-finite x fails it); the range test on the running maximum of |x r|
-    // once for the batch
+    // x r + 1.5 * 2^52, rounded once, holds the integer nearest to the exact
+    // product x r (ties to even) in its low mantissa bits while |x r| < 2^51:
+    // its low dword is k mod 2^32, and k = s - 1.5 * 2^52 exactly. The
+    // near-half test looks at x r - k (rounded once), as a ballot mask (false
+    // for NaN, so a non-finite x fails it); the range test on the running
+    // maximum of |k| once for the batch (a product past 2^51 gives |k| past
+    // it too).
     uint64_t near = 0;
-    double vmax = 0.0;
+    double kmax = 0.0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const double v = (double)xv[i][j] * r;
-            const double k = __builtin_rint(v);
-            near |= ballot(!(__builtin_fabs(v - k) <= kNearHalf));
-            vmax = __builtin_fmax(vmax, __builtin_fabs(v));
-            q[i][j] = (uint32_t)(int32_t)k;
+            const double xd = (double)xv[i][j];
+            const double s = __builtin_fma(xd, r, kRoundShift);
+            const double k = s - kRoundShift;
+            near |= ballot(!(__builtin_fabs(__builtin_fma(xd, r, -k)) <= kNearHalf));
+            kmax = __builtin_fmax(kmax, __builtin_fabs(k));
+            q[i][j] = (uint32_t)__builtin_bit_cast(uint64_t, s);
         }
     }
-    const bool slow = near != 0 || !(vmax <= kFastMax);
+    const bool slow = near != 0 || !(kmax <= kFastMax);
     if (__builtin_expect(ballot(slow) != 0, 0)) {  // slow is wave-uniform except for vmax
         bool out = false;
 #pragma unroll

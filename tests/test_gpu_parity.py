@@ -213,9 +213,10 @@ def test_error_statuses(ref):
         for mode in ("abs", "rel"):
             for pad in ("zero", "global_mean", "global_min"):
                 G.parity(ref, y, 1e-3, mode, 8, pad, 512)
-    y = x.copy()
-    y[10, 10] = 1e7
-    G.parity(ref, y, 1e-3, "abs", 8, "zero", 512)  # ERANGE
+    for big in (1e7, 3e13, 3e38):  # |x / 2eb| past 2^31, past 2^53, past the float range
+        y = x.copy()
+        y[10, 10] = big
+        G.parity(ref, y, 1e-3, "abs", 8, "zero", 512)  # ERANGE
     G.parity(ref, F.constant_field((50, 60), 2.5), 1e-3, "rel", 8, "zero", 512)  # EINVAL
 
 
