@@ -392,33 +392,43 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kWaves + wave;
     if (t >= a.g.n_tiles) return;
-    // the bound: every wave reduces the value-range partials itself
+    // the bound: every wave reduces the value-range partials itself; the
+    // call's status is loaded together with the partials
     uint4 pp[kBoundPer];
     bound_fetch(a.bound, pp, lane);
-    const Bound bd = bound_finish(a.bound, pp, lane);
-    if (a.bound.nparts && t == 0 && lane == 0) {
-        *a.eb_out = bd.eb;
-        if (bd.status != ST_OK) __hip_atomic_store(a.status, bd.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (bd.status != ST_OK || __builtin_nontemporal_load(a.status) != ST_OK) {
-        if (lane == 0) a.tile_count[t] = 0;
-        return;
-    }
+    const int st_in = __builtin_nontemporal_load(a.status);
     WaveCtx w{sbuf_all[wave], 0u, 0u, t, lane};
-    const double r = bd.r, twoeb = bd.twoeb, eb = bd.eb;
+    double r = 0.0, twoeb = 0.0, eb = 0.0;
     uint32_t gpad = 0;
-    if (a.pad_mode == PAD_GLOBAL) {
-        gpad = (uint32_t)round_mean((long long)a.sc->sumq, (long long)a.g.N);
-        if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
-    } else if (a.pad_mode == PAD_GLOBAL_MIN || a.pad_mode == PAD_GLOBAL_MAX) {
-        // rounding to the nearest integer is monotone, so the extreme of q
-        // is the pre-quantised extreme of x (an out-of-range one fails the
-        // call through its own element)
-        const float xe = a.pad_mode == PAD_GLOBAL_MIN ? bd.mn : bd.mx;
-        const double k = exact_round(xe, __builtin_rint((double)xe * r), twoeb, eb);
-        gpad = (uint32_t)(int32_t)(__builtin_fabs(k) <= kQMax ? k : 0.0);
-        if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
-    }
+    // false (and the tile's count 0) when the call has already failed
+    auto prologue = [&]() -> bool {
+        const Bound bd = bound_finish(a.bound, pp, lane);
+        if (a.bound.nparts && t == 0 && lane == 0) {
+            *a.eb_out = bd.eb;
+            if (bd.status != ST_OK) __hip_atomic_store(a.status, bd.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (bd.status != ST_OK || st_in != ST_OK) {
+            if (lane == 0) a.tile_count[t] = 0;
+            return false;
+        }
+        r = bd.r;
+        twoeb = bd.twoeb;
+        eb = bd.eb;
+        if (a.pad_mode == PAD_GLOBAL) {
+            gpad = (uint32_t)round_mean((long long)a.sc->sumq, (long long)a.g.N);
+            if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
+        } else if (a.pad_mode == PAD_GLOBAL_MIN || a.pad_mode == PAD_GLOBAL_MAX) {
+            // rounding to the nearest integer is monotone, so the extreme of q
+            // is the pre-quantised extreme of x (an out-of-range one fails the
+            // call through its own element)
+            const float xe = a.pad_mode == PAD_GLOBAL_MIN ? bd.mn : bd.mx;
+            const double k = exact_round(xe, __builtin_rint((double)xe * r), twoeb, eb);
+            gpad = (uint32_t)(int32_t)(__builtin_fabs(k) <= kQMax ? k : 0.0);
+            if (t == 0 && lane == 0) a.pads[0] = (int32_t)gpad;
+        }
+        return true;
+    };
+    if (!prologue()) return;
     const uint32_t tx = t % a.g.ntx;
     const uint32_t rr = t / a.g.ntx;
     const uint32_t by = rr % a.g.nby;
