@@ -63,7 +63,9 @@ typedef enum {
     DQ_ERANGE = -2,     /* (device) non-finite input, or |q| > 2^31 - 1 */
     DQ_ECAPACITY = -3,  /* (device) more outliers than out_cap; n_out is exact */
     DQ_ENOTSUP = -4,    /* valid but not supported by the GPU kernels (block
-                           not a power of two, or beyond the supported edge) */
+                           not a power of two, beyond the supported edge, or
+                           a 2-D block of 128 / 256 over rows whose length
+                           is not a multiple of block / 64) */
     DQ_EDEVICE = -5,    /* a HIP runtime call failed */
     DQ_ECORRUPT = -6    /* (device, decompress) codes and outliers disagree */
 } dq_status;

@@ -58,6 +58,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python paper_2201_04614_amd/csrc/build.py`")
+        # torch first: its HIP runtime (soname libamdhip64.so.7, which
+        # libtorch_hip requests under another file name) must be the one in
+        # the process when libdq.so resolves that soname; loaded the other
+        # way round the process holds two HIP runtimes and libdq cannot use
+        # torch's streams
+        _torch()
         L = C.CDLL(LIB_PATH)
         P, vp, u64, pu64 = C.POINTER(Params), C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64)
         sig = {

@@ -48,6 +48,10 @@ dq_status validate(const dq_params* p, bool check_eb) {
     // GPU kernel coverage
     const int maxb = p->ndim == 1 ? 4096 : (p->ndim == 2 ? 256 : 64);
     if (!is_pow2(p->block) || p->block > maxb) return DQ_ENOTSUP;
+    // 2-D blocks wider than a wave step of single cells (128, 256) exist
+    // only with block / 64 or more cells per lane, whose row starts must be
+    // aligned to that width
+    if (p->ndim == 2 && p->block > 64 && p->shape[1] % (p->block / 64) != 0) return DQ_ENOTSUP;
     return DQ_OK;
 }
 

@@ -65,9 +65,11 @@ def test_validate_host_only(L):
     p.ndim = 4
     assert dq.validate(p) == dq.DQ_EINVAL
     # valid for the method, outside the GPU kernels' coverage
-    for shape, B in (((100,), 6), ((100,), 8192), ((64, 64), 512), ((8, 8, 8), 128)):
+    for shape, B in (((100,), 6), ((100,), 8192), ((64, 64), 512), ((8, 8, 8), 128), ((436, 207), 128),
+                     ((10, 66), 256)):
         assert dq.validate(dq.make_params(shape, 1e-3, "abs", B)) == dq.DQ_ENOTSUP
-    for shape, B in (((100,), 4096), ((64, 64), 256), ((8, 8, 8), 64), ((5, 7, 9), 1)):
+    for shape, B in (((100,), 4096), ((64, 64), 256), ((8, 8, 8), 64), ((5, 7, 9), 1), ((207, 436), 128),
+                     ((3, 68), 256), ((436, 207), 64)):
         assert dq.validate(dq.make_params(shape, 1e-3, "abs", B)) == dq.DQ_OK
 
 
@@ -96,3 +98,19 @@ def test_null_pointers_rejected_before_any_launch(L):
     assert L.dq_decompress(hp, -1.0, None, None, None, 0, None, None, None, None, 0, None,
                            None) == dq.DQ_EINVAL
     assert L.dq_result_sync(None, None, None) == dq.DQ_EINVAL
+
+
+def test_one_hip_runtime_whatever_loads_first():
+    """The binding opens libdq.so after torch, so the library binds to torch's
+    HIP runtime even when a libdq call comes before any torch use (a second
+    runtime in the process could not use torch's streams)."""
+    import subprocess
+    import sys
+    code = ("from paper_2201_04614_amd import binding as dq\n"
+            "dq.lib()\n"
+            "import torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps').read().splitlines() if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1", r.stdout
