@@ -64,7 +64,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("dq_device.hpp", "dq_kernels.hpp", "dq_encode.hip", "dq_decode.hip", "dq_aux.hip")
+KERNEL_SOURCES = ("dq_device.hpp", "dq_kernels.hpp", "dq_fastdiv.hpp", "dq_encode.hip", "dq_decode.hip", "dq_aux.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "encode_256cubed_traffic.txt")
 
 

@@ -13,6 +13,7 @@
 // and ECAPACITY (decided by the scan when no other error occurred); decode
 // only reports ECORRUPT.
 #include "dq_device.hpp"
+#include "dq_fastdiv.hpp"
 #include "dq_kernels.hpp"
 
 namespace dq {
@@ -424,31 +425,6 @@ void launch_place(const Staging& stg, const Scalars* sc, void* res, uint64_t out
 }
 
 // ------------------------------------------------------------------ decompress
-
-// Unsigned 32-bit division by a divisor fixed for the launch: a multiply-high
-// and two shifts (the round-up method of Granlund and Montgomery, "Division by
-// invariant integers using multiplication", 1994). With l = ceil(log2 d) and
-// m = floor(2^32 (2^l - d) / d) + 1 (which fits in 32 bits),
-//     n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0),  t = mulhi(m, n),
-// exactly, for every 32-bit n.
-struct FastDiv {
-    uint32_t d, m, s1, s2;
-    __device__ __forceinline__ uint32_t div(uint32_t n) const {
-        const uint32_t t = __umulhi(m, n);
-        return (t + ((n - t) >> s1)) >> s2;
-    }
-};
-
-static FastDiv make_fastdiv(uint32_t d) {
-    uint32_t l = 0;
-    while (l < 32 && (1ull << l) < (unsigned long long)d) ++l;
-    FastDiv f;
-    f.d = d;
-    f.m = (uint32_t)((((unsigned __int128)1 << 32) * ((1ull << l) - d)) / d + 1);
-    f.s1 = l < 1 ? l : 1u;
-    f.s2 = l > 1 ? l - 1 : 0u;
-    return f;
-}
 
 struct IndexGeom {
     Geom g;
