@@ -263,6 +263,8 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     stg.region = reinterpret_cast<uint4*>(w + L.region);
     stg.ovf = reinterpret_cast<uint4*>(w + L.ovf);
     stg.ovf_cap = (uint32_t)cap;
+    stg.bcells = (uint32_t)pl.B * (pl.dim >= 2 ? (uint32_t)pl.B : 1u) * (pl.dim == 3 ? (uint32_t)pl.B : 1u);
+    stg.dense = (stg.spt > 0 && (uint64_t)pl.g.bpt * stg.bcells <= 2ull * stg.spt) ? 1u : 0u;
     int32_t* status = &res->status;
 
     uint4* parts = reinterpret_cast<uint4*>(w + L.parts);

@@ -200,6 +200,38 @@ void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream) {
 // tiles' staging regions; k_scatter_overflow places the overflow list, whose
 // entries may belong to any tile.
 
+// Dense staging: a wave copies tile t's outliers, block by block, from
+// their slots to the list (tile offset toff, total outliers of the tile
+// `total`): the block's run starts at its in-tile prefix, origin first.
+// Positions at or past n are not written.
+__device__ __forceinline__ void place_tile_dense(const Staging& stg, const Geom& g, uint32_t t, uint32_t toff,
+                                                 uint32_t total, const uint32_t* __restrict__ block_info,
+                                                 uint32_t n, uint32_t* __restrict__ out_idx,
+                                                 int32_t* __restrict__ out_val, int lane) {
+    const uint32_t tx = t % g.ntx;
+    const uint32_t bx0 = tx * g.bpt;
+    const uint32_t nb = min(g.bpt, g.nbx - bx0);
+    const uint32_t blk0 = (t / g.ntx) * g.nbx + bx0;
+    const uint2* reg = reinterpret_cast<const uint2*>(stg.region + (uint64_t)t * stg.spt);
+    uint32_t info = block_info[blk0];
+    for (uint32_t j = 0; j < nb; ++j) {
+        const uint32_t next = j + 1 < nb ? block_info[blk0 + j + 1] : 0u;
+        const uint32_t cur = info & ~kOriginFlag;
+        const uint32_t end = j + 1 < nb ? (next & ~kOriginFlag) : total;
+        const uint32_t cnt = end - cur;  // at most the block's cells
+        const uint2* src = reg + (uint64_t)j * stg.bcells + ((info & kOriginFlag) ? 0u : 1u);
+        for (uint32_t r = (uint32_t)lane; r < cnt; r += 64) {
+            const uint2 e = src[r];
+            const uint32_t pos = toff + cur + r;
+            if (pos < n) {
+                out_idx[pos] = e.x;
+                out_val[pos] = (int32_t)e.y;
+            }
+        }
+        info = next;
+    }
+}
+
 __device__ __forceinline__ uint32_t block_sum256(uint32_t v, uint32_t* red, int lane, int wave) {
     const uint32_t incl = wave_scan_incl(v, lane);
     if (lane == 63) red[wave] = incl;
@@ -224,7 +256,8 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* 
                                                         uint32_t* __restrict__ tile_off,
                                                         const uint32_t* __restrict__ chunk_sum, uint32_t n_tiles,
                                                         uint32_t n_chunks, const uint32_t* __restrict__ block_info,
-                                                        uint32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
+                                                        Geom g, uint32_t* __restrict__ out_idx,
+                                                        int32_t* __restrict__ out_val) {
     __shared__ uint32_t red[4], red2[4];
     __shared__ uint32_t eoff[kChunkTiles + 1];  // exclusive prefix of the region entries per tile
     __shared__ uint32_t toff_s[kChunkTiles];
@@ -267,6 +300,15 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* 
     }
     __syncthreads();
     if (total == 0 || total > out_cap || load_status(&res->status) != ST_OK) return;  // nothing, or incomplete
+    if (stg.dense) {  // a wave per tile, the kChunkSplit workgroups of the chunk in turn
+        for (uint32_t i = part * 4u + (uint32_t)wave; i < kChunkTiles; i += kChunkSplit * 4u) {
+            const uint32_t tt = c * kChunkTiles + i;
+            if (tt >= n_tiles) break;
+            const uint32_t k = cnt[tt];
+            if (k) place_tile_dense(stg, g, tt, toff_s[i], k, block_info, total, out_idx, out_val, lane);
+        }
+        return;
+    }
     const uint32_t E = eoff[kChunkTiles];
     const uint64_t rbase = (uint64_t)c * kChunkTiles * stg.spt;
     // flattened walk over the chunk's region entries, four per thread at a
@@ -318,9 +360,9 @@ void launch_chunked_place(const Staging& stg, const Scalars* sc, void* res, uint
     const uint32_t n_chunks = (n_tiles + kChunkTiles - 1) / kChunkTiles;
     hipLaunchKernelGGL(k_chunk_sums, dim3(n_chunks), dim3(256), 0, stream, tile_count, n_tiles, chunk_sum);
     hipLaunchKernelGGL(k_scatter_chunks, dim3(n_chunks * kChunkSplit), dim3(256), 0, stream, stg, (ResultDev*)res,
-                       out_cap, tile_count, tile_off, (const uint32_t*)chunk_sum, n_tiles, n_chunks, block_info,
+                       out_cap, tile_count, tile_off, (const uint32_t*)chunk_sum, n_tiles, n_chunks, block_info, g,
                        out_idx, out_val);
-    if (stg.ovf_cap > 0)
+    if (stg.ovf_cap > 0 && !stg.dense)
         hipLaunchKernelGGL(k_scatter_overflow, dim3(1024), dim3(256), 0, stream, stg, sc, (const ResultDev*)res,
                            (const uint32_t*)tile_off, block_info, g, out_idx, out_val);
 }
@@ -400,6 +442,13 @@ __global__ __launch_bounds__(256) void k_place(Staging stg, const Scalars* sc, R
     __syncthreads();
     if (total == 0 || total > out_cap || load_status(&res->status) != ST_OK) return;  // nothing, or incomplete
     const uint32_t n = (uint32_t)total;
+    if (stg.dense) {
+        for (uint32_t t = blockIdx.x + (uint32_t)wave * G; t < n_tiles; t += 4u * G) {
+            const uint32_t c = tile_count[t];
+            if (c) place_tile_dense(stg, g, t, pre[t], c, block_info, n, out_idx, out_val, lane);
+        }
+        return;
+    }
     if (stg.spt) {
         for (uint32_t t = blockIdx.x + (uint32_t)wave * G; t < n_tiles; t += 4u * G) {
             const uint32_t c = min(tile_count[t], stg.spt);

@@ -130,6 +130,13 @@ struct Staging {
     uint32_t spt;      // slots per tile (may be 0)
     uint4* ovf;        // overflow list
     uint32_t ovf_cap;
+    // dense: a tile's region holds a slot for every cell (2 spt >= cells per
+    // tile): its region is an array of uint2 (index, residual) where block j
+    // of the tile owns slots j * bcells .. (j + 1) * bcells - 1, its origin
+    // at the first, the non-origin outlier of rank r at 1 + r; the encode
+    // writes every outlier there directly (no LDS staging, no overflow)
+    uint32_t dense;
+    uint32_t bcells;   // cells per block (B^d)
 };
 
 struct EncArgs {

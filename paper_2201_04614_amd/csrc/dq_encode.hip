@@ -58,7 +58,13 @@ struct WaveCtx {
     uint32_t placed;  // entries already in the tile's staging region
     uint32_t t;       // tile
     int lane;
+    uint32_t blk0;    // the tile's first block
 };
+
+// Dense staging: the slots of block blk in the tile's region (see Staging).
+__device__ __forceinline__ uint2* dense_slots(const EncArgs& a, const WaveCtx& w, uint32_t blk) {
+    return reinterpret_cast<uint2*>(a.stg.region + (uint64_t)w.t * a.stg.spt) + (uint64_t)(blk - w.blk0) * a.stg.bcells;
+}
 
 __device__ __forceinline__ void stage_push(const EncArgs& a, WaveCtx& w, uint32_t tot) {
     if (w.scount + tot > (uint32_t)kStageCap) {
@@ -92,6 +98,18 @@ __device__ __forceinline__ void stage_row_outliers(const EncArgs& a, uint32_t& r
         gtot += popc(m[j] & gmask);
     }
     if (tot == 0) return;
+    if (a.stg.dense) {  // straight to the outlier's own slot
+        uint32_t own = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (out[j]) {
+                dense_slots(a, w, blk)[1u + rank + below + own] = make_uint2((uint32_t)(row + x0 + j), u[j] - R);
+                ++own;
+            }
+        }
+        rank += gtot;
+        return;
+    }
     stage_push(a, w, tot);
     uint32_t slot = w.scount, own = 0;
 #pragma unroll
@@ -364,7 +382,9 @@ __device__ __forceinline__ uint32_t enc_block_end(const EncArgs& a, EncState<DIM
         store_codes<V>(a.codes + orow_base + x0, st.dcode);
     }
     const uint64_t mo = ballot(oout);
-    if (mo) {
+    if (mo && a.stg.dense) {
+        if (oout) dense_slots(a, w, blk)[0] = make_uint2((uint32_t)(orow_base + x0), od);
+    } else if (mo) {
         const uint32_t n = popc(mo);
         stage_push(a, w, n);
         if (oout) w.sbuf[w.scount + mbcnt(mo)] = make_uint4((uint32_t)(orow_base + x0), od, blk, kOriginFlag);
@@ -397,7 +417,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     uint4 pp[kBoundPer];
     bound_fetch(a.bound, pp, lane);
     const int st_in = __builtin_nontemporal_load(a.status);
-    WaveCtx w{sbuf_all[wave], 0u, 0u, t, lane};
+    WaveCtx w{sbuf_all[wave], 0u, 0u, t, lane, 0u};
     double r = 0.0, twoeb = 0.0, eb = 0.0;
     uint32_t gpad = 0;
     // false (and the tile's count 0) when the call has already failed
@@ -434,6 +454,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     const uint32_t by = rr % a.g.nby;
     const uint32_t bz = rr / a.g.nby;
     const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    w.blk0 = (bz * a.g.nby + by) * a.g.nbx + tx * a.g.bpt;
 
     uint32_t tile_total = 0;  // outliers in this tile so far (wave-uniform)
     uint64_t bad = 0;         // lanes with |q| out of range or x not finite
@@ -666,7 +687,9 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
                 oout = !inl;
                 store_codes<V>(a.codes + (uint64_t)bx * B, dcode);
             }
-            if (ballot(oout)) {
+            if (ballot(oout) && a.stg.dense) {
+                if (lane == 0) dense_slots(a, w, bx)[0] = make_uint2(bx * B, od);
+            } else if (ballot(oout)) {
                 stage_push(a, w, 1);
                 if (lane == 0) w.sbuf[w.scount] = make_uint4(bx * B, od, bx, kOriginFlag);
                 w.scount = uniform(w.scount + 1);
