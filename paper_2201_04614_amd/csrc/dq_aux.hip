@@ -200,10 +200,13 @@ void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream) {
 // tiles' staging regions; k_scatter_overflow places the overflow list, whose
 // entries may belong to any tile.
 
-// Dense staging: a wave copies tile t's outliers, block by block, from
-// their slots to the list (tile offset toff, total outliers of the tile
-// `total`): the block's run starts at its in-tile prefix, origin first.
-// Positions at or past n are not written.
+// Dense staging: a wave copies tile t's outliers (tile offset toff, `total`
+// of them) from their slots to the list, 64 blocks at a time: lane j reads
+// block j's in-tile prefix, a wave scan gives each block's run, and the
+// lanes then take consecutive list entries (four loads in flight each),
+// finding the block of an entry by a search over the lanes' prefixes. The
+// list positions are consecutive, so the stores coalesce. Positions at or
+// past n are not written.
 __device__ __forceinline__ void place_tile_dense(const Staging& stg, const Geom& g, uint32_t t, uint32_t toff,
                                                  uint32_t total, const uint32_t* __restrict__ block_info,
                                                  uint32_t n, uint32_t* __restrict__ out_idx,
@@ -213,22 +216,45 @@ __device__ __forceinline__ void place_tile_dense(const Staging& stg, const Geom&
     const uint32_t nb = min(g.bpt, g.nbx - bx0);
     const uint32_t blk0 = (t / g.ntx) * g.nbx + bx0;
     const uint2* reg = reinterpret_cast<const uint2*>(stg.region + (uint64_t)t * stg.spt);
-    uint32_t info = block_info[blk0];
-    for (uint32_t j = 0; j < nb; ++j) {
-        const uint32_t next = j + 1 < nb ? block_info[blk0 + j + 1] : 0u;
+    for (uint32_t j0 = 0; j0 < nb; j0 += 64) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        const bool in = j < nb;
+        const uint32_t info = in ? block_info[blk0 + j] : 0u;
+        const uint32_t nxt = (j + 1 < nb) ? (block_info[blk0 + j + 1] & ~kOriginFlag) : total;
         const uint32_t cur = info & ~kOriginFlag;
-        const uint32_t end = j + 1 < nb ? (next & ~kOriginFlag) : total;
-        const uint32_t cnt = end - cur;  // at most the block's cells
-        const uint2* src = reg + (uint64_t)j * stg.bcells + ((info & kOriginFlag) ? 0u : 1u);
-        for (uint32_t r = (uint32_t)lane; r < cnt; r += 64) {
-            const uint2 e = src[r];
-            const uint32_t pos = toff + cur + r;
-            if (pos < n) {
-                out_idx[pos] = e.x;
-                out_val[pos] = (int32_t)e.y;
+        const uint32_t cnt = in ? min(nxt - cur, stg.bcells) : 0u;  // at most the block's cells
+        const uint32_t skip = (info & kOriginFlag) ? 0u : 1u;
+        const uint32_t incl = wave_scan_incl(cnt, lane);
+        const uint32_t excl = incl - cnt;               // lanes past nb: the chunk's total
+        const uint32_t E = readlane(incl, 63);
+        const uint32_t base = toff + readlane(cur, 0);  // list position of the chunk's first entry
+        for (uint32_t k0 = 0; k0 < E; k0 += 256) {
+            uint2 e[4];
+            bool ok[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t q = k0 + (uint32_t)u * 64u + (uint32_t)lane;
+                ok[u] = q < E;
+                // the last lane (block) whose exclusive prefix is <= q
+                int l = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const uint32_t v = (uint32_t)__shfl((int)excl, l + step);
+                    if (v <= q) l += step;
+                }
+                const uint32_t r = q - (uint32_t)__shfl((int)excl, l);
+                const uint32_t sk = (uint32_t)__shfl((int)skip, l);
+                e[u] = ok[u] ? reg[(uint64_t)(j0 + (uint32_t)l) * stg.bcells + sk + r] : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t pos = base + k0 + (uint32_t)u * 64u + (uint32_t)lane;
+                if (ok[u] && pos < n) {
+                    out_idx[pos] = e[u].x;
+                    out_val[pos] = (int32_t)e[u].y;
+                }
             }
         }
-        info = next;
     }
 }
 
