@@ -70,12 +70,19 @@ def assert_same_compress(g, c, ctx=""):
 
 
 def parity(ref, x, eb, eb_mode="abs", block=16, pad="zero", radius=512, nthreads=0,
-           check_decode=True, x_dev=None, vec=0, pads=None):
-    """Full comparison of compress and decompress; returns the oracle result."""
-    ctx = f"shape={x.shape} eb={eb} {eb_mode} B={block} pad={pad} R={radius}"
+           check_decode=True, x_dev=None, vec=0, pads=None, out_cap=None):
+    """Full comparison of compress and decompress; returns the oracle result.
+    out_cap: outlier capacity of the GPU call (default: the cell count); below
+    the oracle's count the call must fail with ECAPACITY, report the true
+    count and still write the oracle's codes."""
+    ctx = f"shape={x.shape} eb={eb} {eb_mode} B={block} pad={pad} R={radius} cap={out_cap}"
     p = ref.params(x.shape, eb, eb_mode, block, pad, radius)
     c = ref.compress(p, x, nthreads=nthreads, pads=pads)
-    g = gpu_compress(x, eb, eb_mode, block, pad, radius, x_dev=x_dev, vec=vec, pads=pads)
+    g = gpu_compress(x, eb, eb_mode, block, pad, radius, out_cap=out_cap, x_dev=x_dev, vec=vec, pads=pads)
+    if out_cap is not None and c.status == 0 and c.n_out > out_cap:
+        assert g["status"] == dq.DQ_ECAPACITY and g["n_out"] == c.n_out, (ctx, g["status"], g["n_out"], c.n_out)
+        assert np.array_equal(g["codes"].ravel(), c.codes.ravel()), ctx
+        return c
     assert_same_compress(g, c, ctx)
     if c.status == 0 and check_decode:
         st, xr = ref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads, nthreads=nthreads)

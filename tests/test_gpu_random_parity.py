@@ -1,8 +1,11 @@
 """Randomized parity sweep: seeded random shapes (1-D, 2-D, 3-D, ragged),
 block edges, vector-width hints, padding modes, radii, absolute and relative
-bounds and value distributions (uniform, power-law random fields, integers,
-magnitudes from 1e-20 to 1e20); every output of the HIP path must equal the
-oracle's bit for bit (codes, outliers, pads, bound, decoded floats, status)."""
+bounds, value distributions (uniform, power-law random fields, integers,
+magnitudes from 1e-20 to 1e20) and outlier capacities (the cell count, which
+gives every cell a staging slot; a sixteenth of it; the exact count, which
+sends entries to the overflow list; one short, which must fail with
+ECAPACITY); every output of the HIP path must equal the oracle's bit for bit
+(codes, outliers, pads, bound, decoded floats, status)."""
 
 import numpy as np
 import pytest
@@ -50,6 +53,11 @@ def _case(rng):
     return x, eb, mode, B, pad, R, vec, kind
 
 
+def ref_count(ref, x, eb, mode, B, pad, R):
+    c = ref.compress(ref.params(x.shape, eb, mode, B, pad, R), x)
+    return c.status, int(c.n_out)
+
+
 @pytest.mark.parametrize("seed", [101, 202, 303])
 def test_random_configurations(ref, seed):
     rng = np.random.default_rng(seed)
@@ -58,8 +66,14 @@ def test_random_configurations(ref, seed):
         x, eb, mode, B, pad, R, vec, kind = _case(rng)
         if dq.validate(dq.make_params(x.shape, eb, mode, B, pad, R)) == dq.DQ_ENOTSUP:
             continue  # outside the GPU kernels' coverage (checked on the host)
+        cap_kind = int(rng.integers(0, 4))
+        cap = None
+        if cap_kind:
+            st, n_out = ref_count(ref, x, eb, mode, B, pad, R)
+            if st == 0:
+                cap = [max(n_out, x.size // 16), n_out, max(n_out - 1, 0)][cap_kind - 1]
         G.say(f"random seed={seed} case={case} shape={x.shape} B={B} vec={vec} pad={pad} R={R} "
-              f"kind={kind} {mode} eb={eb:.3g}")
-        G.parity(ref, x, eb, mode, B, pad, R, vec=vec)
+              f"kind={kind} {mode} eb={eb:.3g} cap={cap}")
+        G.parity(ref, x, eb, mode, B, pad, R, vec=vec, out_cap=cap)
         ran += 1
     assert ran >= 15
