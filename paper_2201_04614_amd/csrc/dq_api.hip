@@ -152,7 +152,7 @@ CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     L.cap = cap;
     L.sc = 0;
     L.parts = align_up(sizeof(Scalars));
-    L.tiles = L.parts + align_up(sizeof(uint4) * kMinmaxParts);
+    L.tiles = L.parts + align_up(sizeof(uint2) * kMinmaxParts);
     L.toff = L.tiles + align_up(4 * mt);
     L.csum = L.toff + align_up(4 * mt);
     L.info = L.csum + align_up(4 * ((mt + kChunkTiles - 1) / kChunkTiles));
@@ -267,7 +267,7 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
     stg.dense = (stg.spt > 0 && (uint64_t)pl.g.bpt * stg.bcells <= 2ull * stg.spt) ? 1u : 0u;
     int32_t* status = &res->status;
 
-    uint4* parts = reinterpret_cast<uint4*>(w + L.parts);
+    uint2* parts = reinterpret_cast<uint2*>(w + L.parts);
     AuxArgs aa{x, sc, status, pl.g.N};
     // parts: read but unused without the value-range pass
     BoundArgs bound{parts, 0, p->eb, p->eb_mode == DQ_EB_REL ? 1 : 0};

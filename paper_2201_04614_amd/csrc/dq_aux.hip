@@ -83,7 +83,7 @@ __device__ __forceinline__ void minmax_acc4(const f32x4 v, float& mn, float& mx,
 // wave of the kernels that need the bound combines the partials, see
 // bound_finish). First kernel of a compress call with a relative bound, so
 // it also initialises the call.
-__global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restrict__ x, uint64_t N, uint4* parts,
+__global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restrict__ x, uint64_t N, uint2* parts,
                                                            int vec4, Scalars* sc, ResultDev* res) {
     constexpr int W = kMinmaxThreads / 64;
     __shared__ float smin[W], smax[W], snf[W];
@@ -128,11 +128,11 @@ __global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restri
             mx = __builtin_fmaxf(mx, smax[w]);
             nfa += snf[w];
         }
-        parts[blockIdx.x] = make_uint4(fkey(mn), fkey(mx), nfa != nfa ? 1u : 0u, 0u);
+        parts[blockIdx.x] = make_uint2(fkey(mn), nfa != nfa ? 0xffffffffu : fkey(mx));
     }
 }
 
-int launch_minmax(const AuxArgs& a, uint4* parts, void* res, hipStream_t stream) {
+int launch_minmax(const AuxArgs& a, uint2* parts, void* res, hipStream_t stream) {
     const int vec4 = ((reinterpret_cast<uintptr_t>(a.x) & 15u) == 0) ? 1 : 0;
     uint64_t work = vec4 ? a.N / 4 : a.N;
     uint64_t blocks = (work + 4 * kMinmaxThreads - 1) / (4 * kMinmaxThreads);
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_sumq(const float* __restrict__ x, uint6
                                               int32_t* status, BoundArgs bound) {
     __shared__ long long ssum[4];
     __shared__ int sbad[4];
-    uint4 pp[kBoundPer];
+    uint4 pp[kBoundLoads];
     bound_fetch(bound, pp, threadIdx.x & 63);
     const Bound bd = bound_finish(bound, pp, threadIdx.x & 63);  // an invalid bound is reported by encode
     if (bd.status != ST_OK || load_status(status) != ST_OK) return;

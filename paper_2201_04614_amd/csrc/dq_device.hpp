@@ -110,10 +110,11 @@ struct Scalars {
 
 // The error bound of a compress call as the kernels receive it: either the
 // absolute bound itself, or the relative factor and the per-workgroup
-// partials of the value-range pass (min key, max key, non-finite flag), which
-// each workgroup of the consuming kernel reduces itself.
+// partials of the value-range pass (min key, max key; a max key of all ones
+// marks a non-finite input, since no finite or infinite value maps to it),
+// which each wave of the consuming kernel reduces itself.
 struct BoundArgs {
-    const uint4* parts;  // always a valid address of kBoundParts entries
+    const uint2* parts;  // always a valid, 16-byte aligned address of kBoundParts entries
     int nparts;          // value-range partials (0: no value-range pass)
     double v;            // absolute bound, or the relative factor
     int rel;             // 1: eb = v * (max - min) over the partials
@@ -235,6 +236,34 @@ __device__ __forceinline__ uint32_t wave_shr1(uint32_t v) {
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// A DPP move inside rows of 16 lanes (every source lane exists), kept in a
+// register of its own like wave_shr1.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_row(uint32_t v) {
+    uint32_t s = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+    __asm__("" : "+v"(s));
+    return s;
+}
+
+// Minimum / maximum over the whole wave (all lanes active), returned as a
+// scalar: quad swaps, then the half-row and row mirrors leave every row of 16
+// lanes holding its extreme; the four rows' values are read with readlane.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    v = min(v, dpp_row<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = min(v, dpp_row<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = min(v, dpp_row<0x141>(v));  // row_half_mirror
+    v = min(v, dpp_row<0x140>(v));  // row_mirror
+    return min(min(readlane(v, 0), readlane(v, 16)), min(readlane(v, 32), readlane(v, 48)));
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp_row<0xB1>(v));
+    v = max(v, dpp_row<0x4E>(v));
+    v = max(v, dpp_row<0x141>(v));
+    v = max(v, dpp_row<0x140>(v));
+    return max(max(readlane(v, 0), readlane(v, 16)), max(readlane(v, 32), readlane(v, 48)));
 }
 
 // a value every lane holds identically, kept in a scalar register
@@ -417,43 +446,41 @@ struct Bound {
 };
 
 // At most kBoundParts value-range partials (the value-range pass launches at
-// most that many workgroups), read by a wave as kBoundParts / 64 per lane.
+// most that many workgroups), read by a wave as 16-byte pairs, kBoundLoads
+// per lane.
 constexpr int kBoundParts = 256;
-constexpr int kBoundPer = kBoundParts / 64;
+constexpr int kBoundLoads = kBoundParts / 128;
 
-// Issue the loads of the partials (every lane loads, from a valid address
-// even for an absolute bound, so no path skips them); bound_finish waits.
-__device__ __forceinline__ void bound_fetch(const BoundArgs& b, uint4 (&pp)[kBoundPer], int lane) {
+// Issue the loads of the partials (every lane loads, from the valid address
+// even for an absolute bound, so no path skips them; entries past nparts are
+// ignored); bound_finish waits.
+__device__ __forceinline__ void bound_fetch(const BoundArgs& b, uint4 (&pp)[kBoundLoads], int lane) {
+    const uint4* p2 = reinterpret_cast<const uint4*>(b.parts);
 #pragma unroll
-    for (int k = 0; k < kBoundPer; ++k) {
-        const int i = lane + 64 * k;
-        pp[k] = b.parts[i < b.nparts ? i : 0];
-    }
+    for (int k = 0; k < kBoundLoads; ++k) pp[k] = p2[lane + 64 * k];
 }
 
 // The absolute bound, resolved for a relative one (Section II-B, value-range
 // relative bound): eb = rel * (max - min) over the finite inputs. Wave-wide
 // (no barrier); every lane gets the same result.
-__device__ __forceinline__ Bound bound_finish(const BoundArgs& b, const uint4 (&pp)[kBoundPer], int lane) {
+__device__ __forceinline__ Bound bound_finish(const BoundArgs& b, const uint4 (&pp)[kBoundLoads], int lane) {
     Bound o;
     o.status = ST_OK;
     o.mn = o.mx = 0.0f;
     o.eb = b.v;
     if (b.nparts != 0) {
-        uint32_t kmin = 0xffffffffu, kmax = 0u, nf = 0u;
+        uint32_t kmin = 0xffffffffu, kmax = 0u;
 #pragma unroll
-        for (int k = 0; k < kBoundPer; ++k) {
-            const bool in = lane + 64 * k < b.nparts;
-            kmin = in ? min(kmin, pp[k].x) : kmin;
-            kmax = in ? max(kmax, pp[k].y) : kmax;
-            nf |= in ? pp[k].z : 0u;
+        for (int k = 0; k < kBoundLoads; ++k) {
+            const int i = 2 * (lane + 64 * k);  // partials i (x, y) and i + 1 (z, w)
+            kmin = i < b.nparts ? min(kmin, pp[k].x) : kmin;
+            kmax = i < b.nparts ? max(kmax, pp[k].y) : kmax;
+            kmin = i + 1 < b.nparts ? min(kmin, pp[k].z) : kmin;
+            kmax = i + 1 < b.nparts ? max(kmax, pp[k].w) : kmax;
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
-            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
-            nf |= (uint32_t)__shfl_xor((int)nf, off);
-        }
+        kmin = wave_min_u32(kmin);
+        kmax = wave_max_u32(kmax);
+        const bool nf = kmax == 0xffffffffu;
         o.mn = __uint_as_float(uniform(__float_as_uint(funkey(kmin))));
         o.mx = __uint_as_float(uniform(__float_as_uint(funkey(kmax))));
         if (b.rel) o.eb = b.v * ((double)o.mx - (double)o.mn);

@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     if (t >= a.g.n_tiles) return;
     // the bound: every wave reduces the value-range partials itself; the
     // call's status is loaded together with the partials
-    uint4 pp[kBoundPer];
+    uint4 pp[kBoundLoads];
     bound_fetch(a.bound, pp, lane);
     const int st_in = __builtin_nontemporal_load(a.status);
     WaveCtx w{sbuf_all[wave], 0u, 0u, t, lane, 0u};

@@ -83,7 +83,7 @@ constexpr int kMinmaxParts = kBoundParts;  // value-range partials (one per work
 constexpr int kMinmaxThreads = 1024;
 
 void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream);
-int launch_minmax(const AuxArgs& a, uint4* parts, void* res, hipStream_t stream);
+int launch_minmax(const AuxArgs& a, uint2* parts, void* res, hipStream_t stream);
 void launch_sumq(const AuxArgs& a, const BoundArgs& bound, hipStream_t stream);
 constexpr uint32_t kChunkTiles = 256;  // tiles per chunk of the large-field scan
 constexpr uint32_t kChunkSplit = 8;    // workgroups sharing a chunk's scatter
