@@ -127,6 +127,69 @@ __device__ __forceinline__ void fetch_outliers(const DecArgs& a, const uint32_t 
     }
 }
 
+// The same for every row of a batch at once. A row's entry indices follow
+// from the codes alone, so the loads of all entries past the window are
+// issued before any is used: the batch waits once for them instead of once
+// per row (each wait also covers the code loads prefetched behind it).
+template <int V, int NR, bool FULL>
+__device__ __forceinline__ void fetch_outliers_batch(const DecArgs& a, const uint32_t (&c)[NR][V],
+                                                     uint32_t (&d)[NR][V], uint32_t& rank, uint32_t os, uint32_t oe,
+                                                     uint64_t gmask, uint64_t gbase, uint64_t row_stride, bool xin,
+                                                     uint32_t y0, bool& corrupt, const OutWin& w) {
+    uint32_t wi[NR][V], wv[NR][V];
+    bool zero[NR][V], have[NR][V];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const bool rowin = FULL || y0 + (uint32_t)i < a.g.ny;  // uniform
+        uint64_t m[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            zero[i][j] = rowin && (FULL || xin) && c[i][j] == 0u;
+            m[j] = ballot(zero[i][j]);
+        }
+        uint32_t below = 0, gtot = 0, own = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            below += mbcnt(m[j] & gmask);
+            gtot += popc(m[j] & gmask);
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const uint32_t k = os + rank + below + own;
+            own += zero[i][j] ? 1u : 0u;
+            const uint32_t kk = k - w.base;
+            uint32_t ei = 0, ev = 0;
+            if (w.cnt) {  // uniform: every lane takes part in the shuffle
+                const int src = (int)min(kk, 63u);
+                ei = (uint32_t)__shfl((int)w.idx, src);
+                ev = (uint32_t)__shfl((int)w.val, src);
+            }
+            have[i][j] = zero[i][j] && k < oe;
+            if (have[i][j] && kk >= w.cnt) {
+                ei = a.out_idx[k];
+                ev = (uint32_t)a.out_val[k];
+            }
+            wi[i][j] = ei;
+            wv[i][j] = ev;
+        }
+        rank += gtot;
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (zero[i][j]) {
+                if (have[i][j] && wi[i][j] == (uint32_t)(gbase + (uint64_t)i * row_stride + (uint64_t)j)) {
+                    d[i][j] = wv[i][j];
+                } else {
+                    corrupt = true;
+                    d[i][j] = 0;
+                }
+            }
+        }
+    }
+}
+
 template <int DIM, int B, int V>
 __device__ __forceinline__ void dec_row(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[V], int yl,
                                         uint64_t row, uint32_t x0, bool xin, uint64_t gmask, int lane,
@@ -190,14 +253,23 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
         }
     }
     if (ballot(anyzero)) {  // rare: rows in order, so ranks follow local row-major order
+        if constexpr (NR * V <= 4) {
+            // small batches (the small blocks that outlier-dense fields tune
+            // to): one wait for the whole batch's entries
+            fetch_outliers_batch<V, NR, FULL>(a, c, d, st.rank, st.os, st.oe, gmask,
+                                              ((uint64_t)z * ny + y0) * nx + x0, nx, xin, y0, corrupt, st.win);
+        } else {
+            // larger batches row by row: holding every row's entries would
+            // cost the kernel occupancy on every field, outliers or not
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (!FULL && y0 + i >= ny) continue;  // uniform
-            uint32_t cc[V];
+            for (int i = 0; i < NR; ++i) {
+                if (!FULL && y0 + i >= ny) continue;  // uniform
+                uint32_t cc[V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) cc[j] = (FULL || xin) ? c[i][j] : R;
-            fetch_outliers<V>(a, cc, d[i], st.rank, st.os, st.oe, gmask, ((uint64_t)z * ny + y0 + i) * nx + x0,
-                              corrupt, st.win);
+                for (int j = 0; j < V; ++j) cc[j] = (FULL || xin) ? c[i][j] : R;
+                fetch_outliers<V>(a, cc, d[i], st.rank, st.os, st.oe, gmask,
+                                  ((uint64_t)z * ny + y0 + i) * nx + x0, corrupt, st.win);
+            }
         }
     }
 #pragma unroll
