@@ -20,11 +20,19 @@ selector computes:
   once to fp32, so a GPU implementation can match them bit for bit;
 * the MLP 24 -> 64 -> 64 -> 8 (ReLU; a 5-way padding head and a 3-way block
   size head, softmax cross-entropy each), its gradients and one Adam step,
-  in fp64.
+  in fp64; its bfloat16 inference with fp64 sums and with fp32 accumulation
+  in input order.
 
-Parity of the features, candidates and labels is pinned in tests against
-brute force over block slices; the gradients against central finite
-differences.
+Pins (tests/test_select_oracle.py): statistics, candidates, flags, labels
+and all 24 features of two hand-worked fields (tests/golden); closed forms of
+every statistic and feature on integer-affine fields, partial blocks
+included; candidates and flags against the codec oracle's pads and the origin
+codes of real compressions; super-block costs against real outlier counts;
+the forward passes on a hand-built network (bfloat16 ties, ReLU, the (out, in)
+weight layout), exact agreement of the bf16 forwards with the exact one where
+every value is representable, the fp32 accumulation order on a hand-worked
+cancellation and within the recursive-summation bound; the gradients against
+central finite differences; the first Adam step in closed form.
 """
 
 from __future__ import annotations
@@ -317,3 +325,27 @@ def forward_bf16(theta, X):
     h1 = bf16_round(np.maximum(x @ P["W1"].T + P["b1"], 0.0).astype(np.float32)).astype(np.float64)
     h2 = bf16_round(np.maximum(h1 @ P["W2"].T + P["b2"], 0.0).astype(np.float32)).astype(np.float64)
     return h2 @ P["W3"].T + P["b3"]
+
+
+def _f32_layer(x, W, b):
+    """One layer in fp32: each output starts from its bias and adds the
+    products w_k x_k in input order k = 0, 1, ..., every addition rounded to
+    fp32. x and W hold bfloat16 values, so every product is exact in fp32."""
+    x = np.asarray(x, dtype=np.float32)
+    W = np.asarray(W, dtype=np.float32)
+    acc = np.broadcast_to(np.asarray(b, dtype=np.float32), (x.shape[0], W.shape[0])).copy()
+    for k in range(W.shape[1]):
+        acc = (acc + np.outer(x[:, k], W[:, k]).astype(np.float32)).astype(np.float32)
+    return acc
+
+
+def forward_bf16_f32(theta, X):
+    """Logits of the bfloat16 network (parameters, inputs and hidden
+    activations rounded to bfloat16, as forward_bf16) with fp32 accumulation:
+    the reading of BF16 inference with FP32 accumulation in which each sum is
+    taken in input order from the bias, one fp32 rounding per addition."""
+    P = unpack(bf16_round(np.asarray(theta, dtype=np.float32)).astype(np.float64))
+    x = bf16_round(np.asarray(X, dtype=np.float32))
+    h1 = bf16_round(np.maximum(_f32_layer(x, P["W1"], P["b1"]), np.float32(0)))
+    h2 = bf16_round(np.maximum(_f32_layer(h1, P["W2"], P["b2"]), np.float32(0)))
+    return _f32_layer(h2, P["W3"], P["b3"])

@@ -159,3 +159,194 @@ def test_bf16_rounding_worked_values():
     v = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9, 1 + 2 ** -7 + 2 ** -8, -2.5, 0.1], dtype=np.float32)
     want = np.array([1.0, 1.0, 1 + 2 ** -7, 1 + 2 ** -6, -2.5, 0.10009765625], dtype=np.float32)
     assert np.array_equal(S.bf16_round(v), want)
+
+
+# ------------------------------------------------- hand-worked statistics and features
+
+def _golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "selector_worked.json")) as f:
+        return json.load(f)["cases"]
+
+
+def _fval(v):
+    return np.float32(2.0 / 3.0) if v == "2/3" else np.float32(v)
+
+
+@pytest.mark.parametrize("case", _golden(), ids=lambda c: c["cite"][-22:])
+def test_worked_statistics_candidates_features(case):
+    """Every statistic, candidate, flag, label and feature of two tiny fields
+    equals its hand-derived value (tests/golden/selector_worked.json)."""
+    q = np.array(case["q"], dtype=np.int64)
+    B, R, d = case["block"], case["radius"], q.ndim
+    st = S.block_stats(q, B)
+    gmean = S.round_mean(int(q.sum()), q.size)
+    assert gmean == case["gmean"]
+    assert len(st) == len(case["blocks"])
+    for s, want in zip(st, case["blocks"]):
+        for k in ("qo", "cells", "sum", "min", "max", "mad", "fsum", "fcnt", "rough", "npairs"):
+            assert s[k] == want[k], k
+    cand = S.candidates(st, gmean, d)
+    assert np.array_equal(cand, [w["cand"] for w in case["blocks"]])
+    f = S.features(st, cand, gmean, R, d, B)
+    want = np.array([[_fval(v) for v in w["feat"]] for w in case["blocks"]], dtype=np.float32)
+    for j in range(S.N_FEAT):
+        assert np.array_equal(f[:, j], want[:, j]), f"feature {j}: {f[:, j]} != {want[:, j]}"
+    flags = S.origin_outlier_flags(st, cand, 2)
+    assert np.array_equal(flags, case["flags_r2"])
+    assert np.array_equal(S.pad_labels(flags), case["labels_r2"])
+    f1 = S.features(st, S.candidates(st, gmean, d), gmean, 1, d, B)
+    assert np.array_equal(f1[:, 10], np.array(case["f10_r1"], dtype=np.float32))  # the clamp
+
+
+def _rm_frac(v):
+    """Nearest integer to the rational v, halves toward +infinity."""
+    import fractions
+    return math.floor(fractions.Fraction(v) + fractions.Fraction(1, 2))
+
+
+@pytest.mark.parametrize("shape,B,slopes,q0,R", [
+    ((50,), 8, (3,), 1000, 64),
+    ((50,), 16, (-5,), -300, 32),
+    ((20, 27), 4, (2, 5), 700, 16),
+    ((23, 17), 8, (-3, -1), 40, 128),
+    ((20, 27), 8, (4, -7), 900, 8),
+    ((12, 10, 9), 4, (1, 2, 3), 500, 64),
+    ((11, 13, 9), 4, (-2, -1, -4), -50, 16),
+    ((9, 12, 10), 8, (3, -2, 1), 2000, 256)], ids=str)
+def test_features_affine_closed_forms(shape, B, slopes, q0, R):
+    """q = q0 + sum_a s_a u_a: every statistic and feature has a closed form
+    in the block's origin o and extents e (partial blocks included):
+      min / max = q_o + sum of the negative / positive s_a (e_a - 1);
+      block mean = q_o + sum s_a (e_a - 1) / 2, the mean of the face u_a = 0
+      lacks axis a's term; the field mean is q0 + sum s_a (n_a - 1) / 2;
+      with slopes of one sign, mad = cells * sum |s_a| (e_a - 1) / 2."""
+    from fractions import Fraction as Fr
+    d = len(shape)
+    x = F.affine_integer_field(shape, q0, slopes)
+    q = x.astype(np.int64)  # eb = 0.5: q = x for integer x
+    st = S.block_stats(q, B)
+    gmean = S.round_mean(int(q.sum()), q.size)
+    assert gmean == _rm_frac(q0 + sum(Fr(s * (n - 1), 2) for s, n in zip(slopes, shape)))
+    cand = S.candidates(st, gmean, d)
+    f = S.features(st, cand, gmean, R, d, B)
+    one_sign = all(s >= 0 for s in slopes) or all(s <= 0 for s in slopes)
+
+    def cl(v):
+        return np.float32(min(max(float(v), -S.CLAMP), S.CLAMP))
+
+    for b, sl in enumerate(NP.block_slices(shape, B)):
+        o = [s.start for s in sl]
+        e = [s.stop - s.start for s in sl]
+        cells = int(np.prod(e))
+        qo = q0 + sum(s * oa for s, oa in zip(slopes, o))
+        lo = qo + sum(min(0, s * (ea - 1)) for s, ea in zip(slopes, e))
+        hi = qo + sum(max(0, s * (ea - 1)) for s, ea in zip(slopes, e))
+        bmean = _rm_frac(qo + sum(Fr(s * (ea - 1), 2) for s, ea in zip(slopes, e)))
+        assert (st[b]["qo"], st[b]["min"], st[b]["max"]) == (qo, lo, hi)
+        assert cand[b, 2] == bmean and cand[b, 4] == _rm_frac(Fr(lo + hi, 2))
+        if one_sign:
+            mad = cells * sum(Fr(abs(s) * (ea - 1), 2) for s, ea in zip(slopes, e))
+            assert st[b]["mad"] == mad
+            assert f[b, 17] == cl(Fr(mad) / (cells * R))
+        assert f[b, 15] == cl(Fr(qo - lo, R)) and f[b, 16] == cl(Fr(hi - qo, R))
+        assert f[b, 10] == cl(Fr(hi - lo, R))
+        assert f[b, 11] == cl(Fr(bmean - gmean, R))
+        for a in range(d):
+            ea_mean = _rm_frac(qo + sum(Fr(s * (eb - 1), 2) for k, (s, eb) in enumerate(zip(slopes, e)) if k != a))
+            assert f[b, 12 + a] == cl(Fr(ea_mean - bmean, R)), (b, a)
+        for a in range(d, 3):
+            assert f[b, 12 + a] == 0 and f[b, 18 + a] == 0
+        # origin residual against each candidate: zero, global mean, block mean,
+        # edge-mean effective value (pinned against the codec oracle above), midrange
+        for c, P in enumerate([0, gmean, bmean, int(cand[b, 3]), _rm_frac(Fr(lo + hi, 2))]):
+            assert f[b, c] == cl(Fr(qo - P, R)), (b, c)
+            assert f[b, 5 + c] == cl(Fr(abs(qo - P), R)), (b, c)
+        assert f[b, 21] == cl(Fr(gmean, 64 * R))
+
+
+# ------------------------------------------------- the network's forward passes
+
+def _sparse_theta(entries):
+    P = {name: np.zeros(shp) for name, shp in S.param_layout()}
+    for (name, idx), v in entries.items():
+        P[name][idx] = v
+    return S.pack(P)
+
+
+def test_forward_worked_network():
+    """A hand-built network: hidden-1 unit 0 reads feature 3 with weight 2 and
+    bias -1; hidden-2 unit 5 reads hidden-1 unit 0 with weight 3; logit 6 reads
+    hidden-2 unit 5; logit 2 is the bias 0.5. Weights are stored (out, in)."""
+    theta = _sparse_theta({("W1", (0, 3)): 2.0, ("b1", 0): -1.0, ("W2", (5, 0)): 3.0,
+                           ("W3", (6, 5)): 1.0, ("b3", 2): 0.5})
+    X = np.zeros((4, S.N_FEAT))
+    X[0, 3] = 4.0      # a1 = 7, h2 = 21
+    X[1, 3] = 0.0      # a1 = -1: ReLU gives 0
+    X[2, 4] = 100.0    # another feature: no path to the logits
+    X[3, 3] = 129.0    # a1 = 257: a bfloat16 tie between 256 and 258
+    z, _ = S.forward(theta, X)
+    want = np.zeros((4, S.N_OUT))
+    want[:, 2] = 0.5
+    want[0, 6] = 21.0
+    want[3, 6] = 771.0
+    assert np.array_equal(z, want)
+    zb = S.forward_bf16(theta, X)
+    want[3, 6] = 768.0  # 257 rounds to the even neighbour 256, times 3
+    assert np.array_equal(zb, want)
+    assert np.array_equal(S.forward_bf16_f32(theta, X), want.astype(np.float32))
+
+
+def test_forward_bf16_equals_forward_when_every_value_is_representable():
+    """Integer inputs and sparse integer weights keep every activation an
+    integer below 256, which bfloat16 holds exactly: the bf16 forward (fp64
+    sums) and the fp32-accumulating one then equal the exact forward."""
+    rng = np.random.default_rng(11)
+    P = {}
+    for name, shp in S.param_layout():
+        if name.startswith("W"):
+            w = np.zeros(shp)
+            fan = 3 if name == "W1" else 4
+            for r in range(shp[0]):
+                cols = rng.choice(shp[1], fan, replace=False)
+                w[r, cols] = rng.choice([-1.0, 1.0, 2.0], fan)
+            P[name] = w
+        else:
+            P[name] = rng.integers(-3, 4, shp).astype(np.float64)
+    theta = S.pack(P)
+    X = rng.integers(0, 4, (500, S.N_FEAT)).astype(np.float64)
+    z, (_, a1, h1, a2, h2) = S.forward(theta, X)
+    assert np.abs(h1).max() < 256 and np.abs(h2).max() < 256 and h2.max() > 0
+    assert np.array_equal(S.forward_bf16(theta, X), z)
+    assert np.array_equal(S.forward_bf16_f32(theta, X).astype(np.float64), z)
+
+
+def test_forward_bf16_f32_sums_in_order_in_fp32():
+    """The fp32 accumulation starts from the bias and adds the products in
+    input order: 1 + 2^24 rounds to 2^24 (a tie, to even), and - 2^24 then
+    leaves 0, where the exact sum is 1."""
+    theta = _sparse_theta({("b1", 0): 1.0, ("W1", (0, 0)): 1.0, ("W1", (0, 1)): -1.0,
+                           ("W2", (0, 0)): 1.0, ("W3", (0, 0)): 1.0})
+    X = np.zeros((1, S.N_FEAT))
+    X[0, 0] = X[0, 1] = 2.0 ** 24
+    assert S.forward_bf16(theta, X)[0, 0] == 1.0
+    assert S.forward_bf16_f32(theta, X)[0, 0] == 0.0
+
+
+def test_forward_bf16_f32_within_the_summation_bound():
+    """On random networks the fp32-accumulating forward differs from the
+    fp64-summing one only by rounding: with the same bf16 hidden activations
+    (recomputed from the fp32 pass), each logit is within the recursive
+    summation bound n u sum |terms| (u = 2^-24, n = 65 terms)."""
+    rng = np.random.default_rng(12)
+    theta = (S.init_params(4) + rng.normal(0, 0.05, S.n_params())).astype(np.float32)
+    X = rng.normal(0, 2, (400, S.N_FEAT)).astype(np.float32)
+    P = S.unpack(S.bf16_round(theta).astype(np.float64))
+    x = S.bf16_round(X).astype(np.float64)
+    h1 = S.bf16_round(np.maximum(S._f32_layer(x, P["W1"], P["b1"]), 0)).astype(np.float64)
+    h2 = S.bf16_round(np.maximum(S._f32_layer(h1, P["W2"], P["b2"]), 0)).astype(np.float64)
+    z32 = S.forward_bf16_f32(theta, X).astype(np.float64)
+    exact = h2 @ P["W3"].T + P["b3"]
+    bound = 65 * 2.0 ** -24 * (np.abs(h2) @ np.abs(P["W3"]).T + np.abs(P["b3"]))
+    assert np.all(np.abs(z32 - exact) <= bound)
