@@ -35,8 +35,13 @@
  * Memory: every buffer is owned by the caller. Pointers named x, codes,
  * out_idx, out_val, pads, x_hat, res and ws are DEVICE pointers (hipMalloc
  * or torch CUDA tensors); params and res_host are host pointers. The library
- * allocates nothing and keeps no mutable global state; calls on different
- * streams with different buffers may run concurrently.
+ * allocates nothing. Its mutable global state is a process-wide counter that
+ * tags each decompress call's result (atomic, so calls from several host
+ * threads are safe), the fixed scratch array of dq_compress_noalloc (one per
+ * device) and a table of that array's device addresses (guarded by a lock).
+ * Calls on different streams with different buffers may run concurrently,
+ * except dq_compress_noalloc calls on the same device, which share its
+ * scratch array.
  *
  * Streams: dq_compress and dq_decompress validate on the host, then enqueue
  * their kernels on hip_stream (a hipStream_t; NULL = the null stream) and
@@ -67,7 +72,9 @@ typedef enum {
                            a 2-D block of 128 / 256 over rows whose length
                            is not a multiple of block / 64) */
     DQ_EDEVICE = -5,    /* a HIP runtime call failed */
-    DQ_ECORRUPT = -6    /* (device, decompress) codes and outliers disagree */
+    DQ_ECORRUPT = -6,   /* (device, decompress) codes and outliers disagree */
+    DQ_ENOSCRATCH = -7  /* dq_compress_noalloc: the call needs more workspace
+                           than the fixed scratch array holds */
 } dq_status;
 
 typedef enum { DQ_EB_ABS = 0, DQ_EB_REL = 1 } dq_eb_mode;
@@ -183,6 +190,29 @@ dq_status dq_decompress_dev(const dq_params *p, const dq_result *cres, uint64_t 
                             const uint16_t *codes, const uint32_t *out_idx, const int32_t *out_val,
                             const int32_t *pads, float *x_hat, dq_result *res, void *ws,
                             uint64_t ws_bytes, void *hip_stream, const dq_hooks *hooks);
+
+/* Bytes of the fixed device scratch array that dq_compress_noalloc uses as
+ * its workspace (one array per device, held until the process ends). */
+#define DQ_SCRATCH_BYTES (64ull << 20)
+
+/* dq_compress without a workspace argument and without any allocation: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc). The workspace is a fixed
+ * array of DQ_SCRATCH_BYTES in the library's code object, one per device;
+ * the first call on a device (the current device, which must be the device
+ * of hip_stream) looks up that device's copy once. Arguments, outputs and
+ * errors as dq_compress, plus DQ_ENOSCRATCH (returned before anything is
+ * enqueued) when dq_compress_workspace(p, out_cap) exceeds DQ_SCRATCH_BYTES:
+ * about 32 bytes per outlier of capacity, 4 per block and 8 per tile, e.g. a
+ * 256^3 field with 8^3 blocks fits with out_cap up to ~2 million. No hooks.
+ * Every call on a device shares its array and leaves its contents behind
+ * (the kernels initialise what they read, so nothing needs clearing): calls
+ * that overlap in time on one device - on different streams or from
+ * different host threads - race and corrupt each other's results. Calls
+ * ordered on one stream are safe. */
+dq_status dq_compress_noalloc(const dq_params *p, const float *x, uint16_t *codes,
+                              uint32_t *out_idx, int32_t *out_val, uint64_t out_cap,
+                              int32_t *pads, dq_result *res, void *hip_stream);
 
 /* Copy a device dq_result to the host after waiting for hip_stream. */
 dq_status dq_result_sync(const dq_result *res_dev, dq_result *res_host, void *hip_stream);

@@ -17,13 +17,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdq.so")
 
 DQ_OK, DQ_EINVAL, DQ_ERANGE, DQ_ECAPACITY, DQ_ENOTSUP, DQ_EDEVICE, DQ_ECORRUPT = 0, -1, -2, -3, -4, -5, -6
+DQ_ENOSCRATCH = -7
+DQ_SCRATCH_BYTES = 64 << 20  # the fixed workspace of dq_compress_noalloc (include/dq.h)
 EB_MODES = {"abs": 0, "rel": 1}
 PAD_MODES = {"zero": 0, "block_mean": 1, "edge_mean": 2, "global_mean": 3,
              "block_min": 4, "block_max": 5, "global_min": 6, "global_max": 7, "given": 8}
 
 # every function include/dq.h declares
 EXPORTS = ["dq_validate", "dq_num_blocks", "dq_pad_count", "dq_compress_workspace",
-           "dq_decompress_workspace", "dq_compress", "dq_decompress", "dq_decompress_dev", "dq_result_sync",
+           "dq_decompress_workspace", "dq_compress", "dq_compress_noalloc", "dq_decompress", "dq_decompress_dev",
+           "dq_result_sync",
            "dq_event_create", "dq_event_destroy", "dq_event_elapsed_ms", "dq_strerror"]
 
 
@@ -73,6 +76,7 @@ def lib():
             "dq_compress_workspace": ([P, u64, pu64], C.c_int),
             "dq_decompress_workspace": ([P, pu64], C.c_int),
             "dq_compress": ([P, vp, vp, vp, vp, u64, vp, vp, vp, u64, vp, C.POINTER(Hooks)], C.c_int),
+            "dq_compress_noalloc": ([P, vp, vp, vp, vp, u64, vp, vp, vp], C.c_int),
             "dq_decompress": ([P, C.c_double, vp, vp, vp, u64, vp, vp, vp, vp, u64, vp,
                                C.POINTER(Hooks)], C.c_int),
             "dq_decompress_dev": ([P, vp, u64, vp, vp, vp, vp, vp, vp, vp, u64, vp, C.POINTER(Hooks)], C.c_int),
@@ -283,6 +287,17 @@ class Codec:
                                C.byref(hooks.struct) if hooks else None)
         if st != DQ_OK:
             raise DQError(st, "dq_compress")
+
+    def compress_noalloc_async(self, x, stream=None):
+        """As compress_async, through dq_compress_noalloc: the library's fixed
+        scratch array replaces this codec's workspace."""
+        assert x.is_cuda and x.dtype == _torch().float32 and x.is_contiguous()
+        assert tuple(x.shape) == self.shape
+        st = lib().dq_compress_noalloc(C.byref(self.p), _ptr(x), _ptr(self.codes), _ptr(self.out_idx),
+                                       _ptr(self.out_val), self.out_cap, _ptr(self.pads), _ptr(self.res),
+                                       _stream_handle(stream))
+        if st != DQ_OK:
+            raise DQError(st, "dq_compress_noalloc")
 
     def result(self, stream=None):
         return result_sync(self.res, stream)

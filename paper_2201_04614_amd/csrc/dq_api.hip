@@ -6,6 +6,7 @@
 #include <unistd.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "../../include/dq.h"
 #include "dq_kernels.hpp"
@@ -234,18 +235,30 @@ dq_status dq_decompress_workspace(const dq_params* p, uint64_t* bytes) {
     return DQ_OK;
 }
 
-dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint32_t* out_idx,
-                      int32_t* out_val, uint64_t out_cap, int32_t* pads, dq_result* res, void* ws,
-                      uint64_t ws_bytes, void* hip_stream, const dq_hooks* hooks) {
+}  // extern "C"
+
+namespace {
+
+// Host checks of dq_compress and dq_compress_noalloc that need no workspace.
+dq_status compress_check(const dq_params* p, const float* x, uint16_t* codes, uint32_t* out_idx,
+                         int32_t* out_val, uint64_t out_cap, int32_t* pads, dq_result* res) {
     dq_status st = validate(p, true);
     if (st != DQ_OK) return st;
     uint64_t npads = 0;
     dq_pad_count(p, &npads);
-    if (!x || !codes || !res || !ws) return DQ_EINVAL;
+    if (!x || !codes || !res) return DQ_EINVAL;
     if ((reinterpret_cast<uintptr_t>(res) % 8) != 0) return DQ_EINVAL;
     if (out_cap > 0 && (!out_idx || !out_val)) return DQ_EINVAL;
     if (npads > 0 && !pads) return DQ_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return DQ_EINVAL;
+    return DQ_OK;
+}
+
+// The launch sequence of a compress call over the workspace ws (checked by
+// compress_check first).
+dq_status compress_impl(const dq_params* p, const float* x, uint16_t* codes, uint32_t* out_idx,
+                        int32_t* out_val, uint64_t out_cap, int32_t* pads, dq_result* res, void* ws,
+                        uint64_t ws_bytes, void* hip_stream, const dq_hooks* hooks) {
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return DQ_EINVAL;
     Plan pl;
     if (!make_plan(p, x, codes, pl)) return DQ_ENOTSUP;
     const CompressLayout L = compress_layout(p, out_cap);
@@ -305,6 +318,59 @@ dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint3
                              stream);
     }
     return check_launch();
+}
+
+// Workspace of dq_compress_noalloc: one array per device, in the code object
+// (no allocation call ever makes it), kept until the process ends. Host code
+// never passes the array's name to a kernel (on the host it only stands for
+// the symbol): the device address of each device's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+__device__ __align__(256) char scratch[DQ_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+dq_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DQ_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DQ_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dq_status dq_compress(const dq_params* p, const float* x, uint16_t* codes, uint32_t* out_idx,
+                      int32_t* out_val, uint64_t out_cap, int32_t* pads, dq_result* res, void* ws,
+                      uint64_t ws_bytes, void* hip_stream, const dq_hooks* hooks) {
+    const dq_status st = compress_check(p, x, codes, out_idx, out_val, out_cap, pads, res);
+    if (st != DQ_OK) return st;
+    return compress_impl(p, x, codes, out_idx, out_val, out_cap, pads, res, ws, ws_bytes, hip_stream, hooks);
+}
+
+dq_status dq_compress_noalloc(const dq_params* p, const float* x, uint16_t* codes, uint32_t* out_idx,
+                              int32_t* out_val, uint64_t out_cap, int32_t* pads, dq_result* res,
+                              void* hip_stream) {
+    const dq_status st = compress_check(p, x, codes, out_idx, out_val, out_cap, pads, res);
+    if (st != DQ_OK) return st;
+    // the size check needs no GPU: a call that cannot fit is refused first
+    if (compress_layout(p, out_cap).total > (uint64_t)DQ_SCRATCH_BYTES) return DQ_ENOSCRATCH;
+    void* ws = nullptr;
+    const dq_status sst = scratch_of_current_device(&ws);
+    if (sst != DQ_OK) return sst;
+    // every kernel of the sequence initialises the workspace words it reads
+    // (the call's scalars and counters are written by its first kernel), so
+    // the contents left by an earlier call need no clearing
+    return compress_impl(p, x, codes, out_idx, out_val, out_cap, pads, res, ws, DQ_SCRATCH_BYTES, hip_stream,
+                         nullptr);
 }
 
 }  // extern "C"
@@ -430,6 +496,7 @@ const char* dq_strerror(int status) {
     case DQ_ENOTSUP: return "configuration not supported by the GPU kernels";
     case DQ_EDEVICE: return "HIP runtime error";
     case DQ_ECORRUPT: return "codes and outliers are inconsistent";
+    case DQ_ENOSCRATCH: return "the call needs more workspace than dq_compress_noalloc's fixed scratch holds";
     default: return "unknown status";
     }
 }

@@ -45,7 +45,7 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_strerror(L):
-    for st in (0, -1, -2, -3, -4, -5, -6):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
         assert dq.strerror(st) and "unknown" not in dq.strerror(st)
     assert "unknown" in dq.strerror(42)
 
@@ -114,3 +114,20 @@ def test_one_hip_runtime_whatever_loads_first():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "1", r.stdout
+
+
+def test_noalloc_refuses_oversized_calls_before_any_launch(L):
+    """dq_compress_noalloc checks its workspace need against the fixed scratch
+    size on the host: an outlier capacity beyond it gives DQ_ENOSCRATCH
+    without touching a GPU (none here), the usual checks come first."""
+    p = dq.make_params((256, 256, 256), 1e-3, "rel", 8, "zero", 512)
+    hp = C.byref(p)
+    fake = C.c_void_p(1 << 20)  # never dereferenced: the call returns first
+    need = dq.compress_workspace(p, 4 << 20)
+    assert need > dq.DQ_SCRATCH_BYTES
+    assert L.dq_compress_noalloc(hp, fake, fake, fake, fake, 4 << 20, None, fake, None) == dq.DQ_ENOSCRATCH
+    assert L.dq_compress_noalloc(hp, None, fake, fake, fake, 4 << 20, None, fake, None) == dq.DQ_EINVAL
+    assert L.dq_compress_noalloc(hp, fake, fake, None, None, 1, None, fake, None) == dq.DQ_EINVAL
+    bad = dq.make_params((256, 256, 256), 0.0, "rel", 8, "zero", 512)
+    assert L.dq_compress_noalloc(C.byref(bad), fake, fake, fake, fake, 1, None, fake, None) == dq.DQ_EINVAL
+    assert dq.compress_workspace(p, 1 << 20) <= dq.DQ_SCRATCH_BYTES
