@@ -63,10 +63,13 @@ struct DecState {
 
     // Load the window; every lane's block is valid and lane 63 holds the
     // wave's last block (blocks in lane order), so the wave's outliers are
-    // entries os(lane 0) .. oe(lane 63).
+    // entries os(lane 0) .. oe(lane 63). Block starts lie in [0, n_out] but
+    // need not increase over a list out of order (whose call ends in
+    // ECORRUPT): an empty window then, never a wrapped count.
     __device__ __forceinline__ void prefetch(const DecArgs& a, int lane) {
         win.base = uniform(os);
-        win.cnt = min(readlane(oe, 63) - win.base, 64u);
+        const uint32_t e63 = readlane(oe, 63);
+        win.cnt = e63 > win.base ? min(e63 - win.base, 64u) : 0u;
         if (win.cnt) {
             const uint32_t k = win.base + min((uint32_t)lane, win.cnt - 1u);
             win.idx = a.out_idx[k];

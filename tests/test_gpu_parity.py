@@ -300,3 +300,23 @@ def test_vector_width_hint(ref, vec):
     x1 = F.uniform_field((30000,), seed=8)
     for B in (16, 1024):
         G.parity(ref, x1, 1e-3, "abs", B, "block_mean", 128, vec=vec)
+
+
+def test_shuffled_list_over_many_blocks_is_corrupt(ref):
+    """More blocks than the index kernel's grid covers in one step (2^21 + 1
+    block starts): an outlier list out of order makes the block starts of
+    different workgroups non-monotone; the decode must still read only list
+    entries below n_out and report ECORRUPT."""
+    n = 1 << 21
+    x = (F.uniform_field((n,), seed=21, lo=-1.0, hi=1.0) + np.float32(50.0)).astype(np.float32)
+    p = ref.params(x.shape, 0.5, "abs", 1, "zero", 4)
+    c = ref.compress(p, x, out_cap=n)
+    assert c.status == 0 and c.n_out == n  # every block origin (every cell) is an outlier
+    perm = np.random.default_rng(21).permutation(n)
+    idx, val = c.out_idx[perm], c.out_val[perm]
+    G.say("shuffled outlier list over 2^21 blocks")
+    g = G.gpu_compress(x, 0.5, "abs", 1, "zero", 4, out_cap=n)
+    gs, _ = G.gpu_decompress(g["codec"], c.eb_abs, c.codes, idx, val, c.pads)
+    assert gs == dq.DQ_ECORRUPT
+    rs, _ = ref.decompress(p, c.eb_abs, c.codes, idx, val, c.pads)
+    assert rs == dq.DQ_ECORRUPT
