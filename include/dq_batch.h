@@ -54,6 +54,31 @@ typedef struct dq_batch_graph dq_batch_graph;
 dq_status dq_batch_graph_create(const dq_batch_field *fields, uint64_t n, int branches,
                                 dq_batch_graph **graph);
 
+/* The persistent form of the batch (Section III-F: blocks are independent
+ * work items, here taken from every field at once). The graph holds a fixed
+ * number of kernels whatever the number of fields: one value-range pass
+ * over all fields (which also resolves every field's bound), one persistent
+ * encode per (dimensionality, block, cells per lane) class of the batch
+ * whose waves drain a flattened queue of (field, run of tiles) units with an
+ * atomic ticket, one outlier placement pass over all fields, and one
+ * persistent decode per class. Every field is compressed and decompressed
+ * exactly as dq_compress and dq_decompress_dev would (same streams, same
+ * results in cres / dres).
+ * Needs, beyond dq_batch_graph_create: x_hat != NULL, out_cap >= the field's
+ * cell count, a padding other than DQ_PAD_GLOBAL_MEAN, cws of
+ * dq_compress_workspace(p, out_cap) bytes (256-byte aligned) - else
+ * DQ_ENOTSUP / DQ_EINVAL; dws and dws_bytes are not used. The decode takes
+ * each block's outlier run from the compress call's workspace, so the
+ * graph must be launched as a whole.
+ * ws: device workspace (256-byte aligned) of at least
+ * dq_batch_persistent_workspace bytes, holding the queues and the fields'
+ * arguments; written once here (synchronously), read by every launch, owned
+ * by the caller and kept until dq_batch_graph_destroy. Launches of the same
+ * graph must not overlap (they share the tickets in ws). */
+dq_status dq_batch_persistent_workspace(const dq_batch_field *fields, uint64_t n, uint64_t *bytes);
+dq_status dq_batch_persistent_create(const dq_batch_field *fields, uint64_t n, void *ws, uint64_t ws_bytes,
+                                     dq_batch_graph **graph);
+
 /* Enqueue one execution of the graph on hip_stream. Per-field outcomes land
  * in each field's cres / dres. */
 dq_status dq_batch_graph_launch(dq_batch_graph *graph, void *hip_stream);

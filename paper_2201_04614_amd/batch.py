@@ -4,6 +4,12 @@
     b = Batch([(x0, dict(eb=1e-3, eb_mode="rel", block=8)), (x1, dict(eb=1e-4, block=16)), ...])
     b.launch()             # one graph launch: every field compressed and decompressed
     b.results()            # per field: compress and decompress dq_result
+
+Batch replays every field's own kernels from the graph (over parallel
+branches); PersistentBatch captures a fixed handful of kernels whatever the
+number of fields: persistent encode and decode kernels draining a flattened
+(field, tile) queue with an atomic ticket, one per (dimensionality, block,
+cells per lane) class.
 """
 
 from __future__ import annotations
@@ -13,7 +19,8 @@ import ctypes as C
 from . import binding as dq
 
 # every function include/dq_batch.h declares
-EXPORTS = ["dq_batch_graph_create", "dq_batch_graph_launch", "dq_batch_graph_destroy"]
+EXPORTS = ["dq_batch_graph_create", "dq_batch_graph_launch", "dq_batch_graph_destroy",
+           "dq_batch_persistent_workspace", "dq_batch_persistent_create"]
 
 
 class Field(C.Structure):
@@ -37,6 +44,11 @@ def lib():
         L.dq_batch_graph_launch.restype = C.c_int
         L.dq_batch_graph_destroy.argtypes = [vp]
         L.dq_batch_graph_destroy.restype = C.c_int
+        L.dq_batch_persistent_workspace.argtypes = [C.POINTER(Field), C.c_uint64, C.POINTER(C.c_uint64)]
+        L.dq_batch_persistent_workspace.restype = C.c_int
+        L.dq_batch_persistent_create.argtypes = [C.POINTER(Field), C.c_uint64, vp, C.c_uint64,
+                                                 C.POINTER(C.c_void_p)]
+        L.dq_batch_persistent_create.restype = C.c_int
         _ready = True
     return L
 
@@ -45,30 +57,34 @@ def _p(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _fields(items, decompress=True):
+    codecs = []
+    arr = (Field * len(items))()
+    for k, (x, kw) in enumerate(items):
+        kw = dict(kw)
+        eb = kw.pop("eb")
+        cd = dq.Codec(tuple(x.shape), eb, device=x.device, **kw)
+        codecs.append(cd)
+        f = arr[k]
+        f.p = cd.p
+        f.x, f.codes = _p(x), _p(cd.codes)
+        f.out_idx, f.out_val, f.out_cap = _p(cd.out_idx), _p(cd.out_val), cd.out_cap
+        f.pads, f.cres = _p(cd.pads), _p(cd.res)
+        f.cws, f.cws_bytes = _p(cd.ws_c), cd.ws_c.numel()
+        f.x_hat = _p(cd.x_hat) if decompress else None
+        f.dres, f.dws, f.dws_bytes = _p(cd.dres), _p(cd.ws_d), cd.ws_d.numel()
+    return codecs, arr
+
+
 class Batch:
     """Codecs for a list of (field tensor, codec keyword arguments) and the
     graph that runs all of them. Each x must stay alive and keep its storage."""
 
     def __init__(self, items, branches=4, decompress=True):
         self.items = items
-        self.codecs = []
-        arr = (Field * len(items))()
-        for k, (x, kw) in enumerate(items):
-            kw = dict(kw)
-            eb = kw.pop("eb")
-            cd = dq.Codec(tuple(x.shape), eb, device=x.device, **kw)
-            self.codecs.append(cd)
-            f = arr[k]
-            f.p = cd.p
-            f.x, f.codes = _p(x), _p(cd.codes)
-            f.out_idx, f.out_val, f.out_cap = _p(cd.out_idx), _p(cd.out_val), cd.out_cap
-            f.pads, f.cres = _p(cd.pads), _p(cd.res)
-            f.cws, f.cws_bytes = _p(cd.ws_c), cd.ws_c.numel()
-            f.x_hat = _p(cd.x_hat) if decompress else None
-            f.dres, f.dws, f.dws_bytes = _p(cd.dres), _p(cd.ws_d), cd.ws_d.numel()
-        self._fields = arr
+        self.codecs, self._fields = _fields(items, decompress)
         h = C.c_void_p()
-        st = lib().dq_batch_graph_create(arr, len(items), int(branches), C.byref(h))
+        st = lib().dq_batch_graph_create(self._fields, len(items), int(branches), C.byref(h))
         if st != dq.DQ_OK:
             raise dq.DQError(st, "dq_batch_graph_create")
         self._h = h
@@ -91,3 +107,23 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class PersistentBatch(Batch):
+    """The same batch through dq_batch_persistent_create: every field needs
+    out_cap >= its cell count and a padding other than global_mean."""
+
+    def __init__(self, items):
+        import torch
+        self.items = items
+        self.codecs, self._fields = _fields(items, True)
+        need = C.c_uint64(0)
+        st = lib().dq_batch_persistent_workspace(self._fields, len(items), C.byref(need))
+        if st != dq.DQ_OK:
+            raise dq.DQError(st, "dq_batch_persistent_workspace")
+        self.ws = dq._aligned_bytes(int(need.value), items[0][0].device)
+        h = C.c_void_p()
+        st = lib().dq_batch_persistent_create(self._fields, len(items), _p(self.ws), self.ws.numel(), C.byref(h))
+        if st != dq.DQ_OK:
+            raise dq.DQError(st, "dq_batch_persistent_create")
+        self._h = h

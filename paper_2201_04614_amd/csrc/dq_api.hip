@@ -9,14 +9,13 @@
 #include <mutex>
 
 #include "../../include/dq.h"
-#include "dq_kernels.hpp"
+#include "dq_host.hpp"
 
 using namespace dq;
+using namespace dq::host;
 
-namespace {
-
-constexpr uint64_t kAlign = 256;
-inline uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+namespace dq {
+namespace host {
 
 int ilog2(uint32_t v) {
     int l = 0;
@@ -55,12 +54,6 @@ dq_status validate(const dq_params* p, bool check_eb) {
     if (p->ndim == 2 && p->block > 64 && p->shape[1] % (p->block / 64) != 0) return DQ_ENOTSUP;
     return DQ_OK;
 }
-
-struct Plan {
-    Geom g;
-    int dim, B, V;
-    uint64_t nblocks;
-};
 
 void base_geom(const dq_params* p, Geom& g) {
     const int d = p->ndim;
@@ -135,15 +128,6 @@ uint64_t max_tiles(const dq_params* p) {
     return m;
 }
 
-// Compress workspace: scalars, value-range partials, per-tile counts and
-// offsets, per-chunk count sums, per-block outlier prefixes, then the outlier
-// staging area: per-tile regions of cap entries in all (cap / tiles each),
-// and an overflow list of cap entries (the overflow never exceeds the outlier
-// count, so everything fits whenever the outliers fit the caller's capacity).
-struct CompressLayout {
-    uint64_t sc, parts, tiles, toff, csum, info, region, ovf, cap, total;
-};
-
 CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
     Geom g;
     base_geom(p, g);
@@ -177,6 +161,11 @@ uint32_t next_tag() {
     while (tag == 0) tag = (counter.fetch_add(1) + 1) * 2654435761u ^ salt;
     return tag;
 }
+
+}  // namespace host
+}  // namespace dq
+
+namespace {
 
 dq_status check_launch() {
     return hipGetLastError() == hipSuccess ? DQ_OK : DQ_EDEVICE;
@@ -277,7 +266,9 @@ dq_status compress_impl(const dq_params* p, const float* x, uint16_t* codes, uin
     stg.ovf = reinterpret_cast<uint4*>(w + L.ovf);
     stg.ovf_cap = (uint32_t)cap;
     stg.bcells = (uint32_t)pl.B * (pl.dim >= 2 ? (uint32_t)pl.B : 1u) * (pl.dim == 3 ? (uint32_t)pl.B : 1u);
-    stg.dense = (stg.spt > 0 && (uint64_t)pl.g.bpt * stg.bcells <= 2ull * stg.spt) ? 1u : 0u;
+    // a tile holds at most min(bpt, nbx) blocks
+    const uint64_t tile_blocks_max = pl.g.bpt < pl.g.nbx ? pl.g.bpt : pl.g.nbx;
+    stg.dense = (stg.spt > 0 && tile_blocks_max * stg.bcells <= 2ull * stg.spt) ? 1u : 0u;
     int32_t* status = &res->status;
 
     uint2* parts = reinterpret_cast<uint2*>(w + L.parts);

@@ -45,13 +45,17 @@ __device__ __forceinline__ void init_scalars(Scalars* sc, ResultDev* res) {
 }
 
 // absolute bound given by the caller
-__global__ void k_compress_init(Scalars* sc, ResultDev* res, double eb) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void compress_init(Scalars* sc, ResultDev* res, double eb) {
     init_scalars(sc, res);
     sc->eb = eb;
     sc->twoeb = 2.0 * eb;
     sc->r = 1.0 / (2.0 * eb);
     res->eb_abs = eb;
+}
+
+__global__ void k_compress_init(Scalars* sc, ResultDev* res, double eb) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    compress_init(sc, res, eb);
 }
 
 void launch_compress_init(Scalars* sc, void* res, double eb, hipStream_t stream) {
@@ -83,17 +87,17 @@ __device__ __forceinline__ void minmax_acc4(const f32x4 v, float& mn, float& mx,
 // wave of the kernels that need the bound combines the partials, see
 // bound_finish). First kernel of a compress call with a relative bound, so
 // it also initialises the call.
-__global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restrict__ x, uint64_t N, uint2* parts,
-                                                           int vec4, Scalars* sc, ResultDev* res) {
+__device__ __forceinline__ void minmax_part(const float* __restrict__ x, uint64_t N, uint2* parts, int vec4,
+                                            Scalars* sc, ResultDev* res, uint32_t part, uint32_t nparts) {
     constexpr int W = kMinmaxThreads / 64;
     __shared__ float smin[W], smax[W], snf[W];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (part == 0 && threadIdx.x == 0) {
         init_scalars(sc, res);
         res->eb_abs = 0.0;
     }
     float mn = __builtin_inff(), mx = -__builtin_inff(), nfa = 0.0f;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)part * kMinmaxThreads + threadIdx.x;
+    const uint64_t stride = (uint64_t)nparts * kMinmaxThreads;
     uint64_t start = 0;
     if (vec4) {
         const uint64_t n4 = N / 4;
@@ -128,8 +132,13 @@ __global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restri
             mx = __builtin_fmaxf(mx, smax[w]);
             nfa += snf[w];
         }
-        parts[blockIdx.x] = make_uint2(fkey(mn), nfa != nfa ? 0xffffffffu : fkey(mx));
+        parts[part] = make_uint2(fkey(mn), nfa != nfa ? 0xffffffffu : fkey(mx));
     }
+}
+
+__global__ __launch_bounds__(kMinmaxThreads) void k_minmax(const float* __restrict__ x, uint64_t N, uint2* parts,
+                                                           int vec4, Scalars* sc, ResultDev* res) {
+    minmax_part(x, N, parts, vec4, sc, res, blockIdx.x, gridDim.x);
 }
 
 int launch_minmax(const AuxArgs& a, uint2* parts, void* res, hipStream_t stream) {
@@ -267,29 +276,34 @@ __device__ __forceinline__ uint32_t block_sum256(uint32_t v, uint32_t* red, int 
     return t;
 }
 
-__global__ __launch_bounds__(256) void k_chunk_sums(const uint32_t* __restrict__ cnt, uint32_t n_tiles,
-                                                    uint32_t* __restrict__ chunk_sum) {
+__device__ __forceinline__ void chunk_sum_part(const uint32_t* __restrict__ cnt, uint32_t n_tiles,
+                                               uint32_t* __restrict__ chunk_sum, uint32_t chunk) {
     __shared__ uint32_t red[4];
     const int tid = threadIdx.x;
-    const uint32_t t = blockIdx.x * kChunkTiles + (uint32_t)tid;
+    const uint32_t t = chunk * kChunkTiles + (uint32_t)tid;
     const uint32_t v = t < n_tiles ? cnt[t] : 0u;
     const uint32_t s = block_sum256(v, red, tid & 63, tid >> 6);
-    if (tid == 0) chunk_sum[blockIdx.x] = s;
+    if (tid == 0) chunk_sum[chunk] = s;
 }
 
-__global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* res, uint64_t out_cap,
-                                                        const uint32_t* __restrict__ cnt,
-                                                        uint32_t* __restrict__ tile_off,
-                                                        const uint32_t* __restrict__ chunk_sum, uint32_t n_tiles,
-                                                        uint32_t n_chunks, const uint32_t* __restrict__ block_info,
-                                                        Geom g, uint32_t* __restrict__ out_idx,
-                                                        int32_t* __restrict__ out_val) {
+__global__ __launch_bounds__(256) void k_chunk_sums(const uint32_t* __restrict__ cnt, uint32_t n_tiles,
+                                                    uint32_t* __restrict__ chunk_sum) {
+    chunk_sum_part(cnt, n_tiles, chunk_sum, blockIdx.x);
+}
+
+// Share `part` (of kChunkSplit) of chunk c's placement; the share (0, 0)
+// writes the call's outlier count and capacity verdict.
+__device__ __forceinline__ void scatter_chunk_part(const Staging& stg, ResultDev* res, uint64_t out_cap,
+                                                   const uint32_t* __restrict__ cnt, uint32_t* __restrict__ tile_off,
+                                                   const uint32_t* __restrict__ chunk_sum, uint32_t n_tiles,
+                                                   uint32_t n_chunks, const uint32_t* __restrict__ block_info,
+                                                   const Geom& g, uint32_t* __restrict__ out_idx,
+                                                   int32_t* __restrict__ out_val, const uint32_t c,
+                                                   const uint32_t part) {
     __shared__ uint32_t red[4], red2[4];
     __shared__ uint32_t eoff[kChunkTiles + 1];  // exclusive prefix of the region entries per tile
     __shared__ uint32_t toff_s[kChunkTiles];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t c = blockIdx.x / kChunkSplit;     // chunk
-    const uint32_t part = blockIdx.x % kChunkSplit;  // share of its entries
     // carry of this chunk and the field's total
     uint32_t before = 0, all = 0;
     for (uint32_t i = (uint32_t)tid; i < n_chunks; i += 256u) {
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* 
     toff_s[tid] = off;
     eoff[tid + 1] = wbr + incr;
     if (tid == 0) eoff[0] = 0u;
-    if (blockIdx.x == 0 && tid == 0 && load_status(&res->status) == ST_OK) {
+    if (c == 0 && part == 0 && tid == 0 && load_status(&res->status) == ST_OK) {
         res->n_out = total;
         if (total > out_cap) store_status(&res->status, ST_ECAPACITY);
     }
@@ -362,6 +376,69 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* 
         for (int u = 0; u < 4; ++u)
             if (ok[u]) place_entry(e[u], o[u], block_info, total, out_idx, out_val);
     }
+}
+
+__global__ __launch_bounds__(256) void k_scatter_chunks(Staging stg, ResultDev* res, uint64_t out_cap,
+                                                        const uint32_t* __restrict__ cnt,
+                                                        uint32_t* __restrict__ tile_off,
+                                                        const uint32_t* __restrict__ chunk_sum, uint32_t n_tiles,
+                                                        uint32_t n_chunks, const uint32_t* __restrict__ block_info,
+                                                        Geom g, uint32_t* __restrict__ out_idx,
+                                                        int32_t* __restrict__ out_val) {
+    scatter_chunk_part(stg, res, out_cap, cnt, tile_off, chunk_sum, n_tiles, n_chunks, block_info, g, out_idx,
+                       out_val, blockIdx.x / kChunkSplit, blockIdx.x % kChunkSplit);
+}
+
+// ------------------------------------------------------------------ batches: one launch per stage
+
+// Value-range pass (or the initialisation of a call with an absolute bound)
+// of every field of a batch: workgroup k runs unit k = (field, part). Unit 0
+// also clears the batch's tickets, and part 0 of a field clears its
+// decompress status word (the decompress of a replayed graph then reports
+// its own outcome).
+__global__ __launch_bounds__(kMinmaxThreads) void k_batch_aux(const AuxField* __restrict__ fields,
+                                                              const uint2* __restrict__ units,
+                                                              unsigned int* tickets, uint32_t n_tickets) {
+    const uint2 un = units[blockIdx.x];
+    const AuxField f = fields[un.x];
+    ResultDev* res = reinterpret_cast<ResultDev*>(f.res_);
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < n_tickets; i += blockDim.x) tickets[i] = 0u;
+    if (un.y == 0 && threadIdx.x == 0) *f.dres_word = 0ull;
+    if (f.nparts == 0) {
+        if (threadIdx.x == 0) compress_init(f.sc, res, f.eb);
+        return;
+    }
+    minmax_part(f.x, f.N, f.parts, f.vec4, f.sc, res, un.y, (uint32_t)f.nparts);
+}
+
+// Outlier totals of every 256-tile chunk of every field: unit = (field, chunk).
+__global__ __launch_bounds__(256) void k_batch_chunk_sums(const PlaceField* __restrict__ fields,
+                                                          const uint2* __restrict__ units) {
+    const uint2 un = units[blockIdx.x];
+    const PlaceField& f = fields[un.x];
+    chunk_sum_part(f.cnt, f.n_tiles, f.chunk_sum, un.y);
+}
+
+// Tile offsets and outlier placement of every chunk of every field: unit =
+// (field, chunk), kChunkSplit workgroups each.
+__global__ __launch_bounds__(256) void k_batch_scatter(const PlaceField* __restrict__ fields,
+                                                       const uint2* __restrict__ units) {
+    const uint2 un = units[blockIdx.x / kChunkSplit];
+    const PlaceField f = fields[un.x];
+    scatter_chunk_part(f.stg, reinterpret_cast<ResultDev*>(f.res_), f.out_cap, f.cnt, f.tile_off, f.chunk_sum, f.n_tiles, f.n_chunks, f.block_info,
+                       f.g, f.out_idx, f.out_val, un.y, blockIdx.x % kChunkSplit);
+}
+
+void launch_batch_aux(const AuxField* fields, const uint2* units, uint32_t n_units, unsigned int* tickets,
+                      uint32_t n_tickets, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_aux, dim3(n_units), dim3(kMinmaxThreads), 0, stream, fields, units, tickets,
+                       n_tickets);
+}
+
+void launch_batch_place(const PlaceField* fields, const uint2* units, uint32_t n_units, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_chunk_sums, dim3(n_units), dim3(256), 0, stream, fields, units);
+    hipLaunchKernelGGL(k_batch_scatter, dim3(n_units * kChunkSplit), dim3(256), 0, stream, fields, units);
 }
 
 __global__ __launch_bounds__(256) void k_scatter_overflow(Staging stg, const Scalars* sc, const ResultDev* res,

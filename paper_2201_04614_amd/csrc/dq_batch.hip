@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <numeric>
 #include <vector>
 
 #include "../../include/dq.h"
 #include "../../include/dq_batch.h"
+#include "dq_host.hpp"
 
 struct dq_batch_graph {
     hipGraph_t graph = nullptr;
@@ -34,7 +36,297 @@ uint64_t cells(const dq_params& p) {
     return n;
 }
 
+// ------------------------------------------------------------------ persistent batches
+
+using namespace dq;
+using namespace dq::host;
+
+constexpr uint32_t kUnitTiles = 4;  // tiles per ticket of the persistent encode / decode
+
+// The queue and field tables of a persistent batch, in the caller's workspace.
+struct PersistentLayout {
+    uint64_t enc, dec, aux, place, aux_units, chunk_units, class_units, tickets, total;
+    uint32_t n_aux_units, n_chunk_units, n_class_units;
+    std::vector<int> cls;                          // class of every field
+    std::vector<std::array<int, 3>> classes;       // (dim, block, v)
+    std::vector<Plan> plans;
+};
+
+int minmax_parts(uint64_t N, bool vec4) {
+    const uint64_t work = vec4 ? N / 4 : N;
+    uint64_t b = (work + 4 * kMinmaxThreads - 1) / (4 * kMinmaxThreads);
+    if (b > (uint64_t)kMinmaxParts) b = kMinmaxParts;
+    return (int)(b < 1 ? 1 : b);
+}
+
+bool needs_range(const dq_params& p) {
+    return p.eb_mode == DQ_EB_REL || p.pad_mode == DQ_PAD_GLOBAL_MIN || p.pad_mode == DQ_PAD_GLOBAL_MAX;
+}
+
+// Checks every field and plans the batch (no device access).
+dq_status persistent_plan(const dq_batch_field* fields, uint64_t n, PersistentLayout& L) {
+    if (!fields || n == 0 || n > 0xffffffffull) return DQ_EINVAL;
+    L.plans.resize(n);
+    L.cls.resize(n);
+    uint64_t aux_units = 0, chunk_units = 0, class_units = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const dq_batch_field& f = fields[i];
+        const dq_params* p = &f.p;
+        dq_status st = validate(p, true);
+        if (st != DQ_OK) return st;
+        uint64_t npads = 0;
+        dq_pad_count(p, &npads);
+        if (!f.x || !f.codes || !f.out_idx || !f.out_val || !f.cres || !f.cws || !f.x_hat || !f.dres)
+            return DQ_EINVAL;
+        if (npads > 0 && !f.pads) return DQ_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(f.cres) % 8) || (reinterpret_cast<uintptr_t>(f.dres) % 8) ||
+            (reinterpret_cast<uintptr_t>(f.cws) % kAlign))
+            return DQ_EINVAL;
+        if (p->pad_mode == DQ_PAD_GLOBAL_MEAN) return DQ_ENOTSUP;  // needs its own pass over q
+        Plan pl;
+        if (!make_plan(p, f.x, f.codes, pl)) return DQ_ENOTSUP;
+        Geom g0;
+        base_geom(p, g0);
+        if (f.out_cap < g0.N) return DQ_ENOTSUP;  // dense staging only
+        const CompressLayout cl = compress_layout(p, f.out_cap);
+        if (f.cws_bytes < cl.total) return DQ_EINVAL;
+        // the decode runs on the compress call's tiling, so x_hat must allow
+        // its V too; and every tile's region must hold a slot per cell of its
+        // blocks (dense staging): else fewer cells per lane
+        const uint32_t bcells = (uint32_t)pl.B * (pl.dim >= 2 ? (uint32_t)pl.B : 1u) * (pl.dim == 3 ? (uint32_t)pl.B : 1u);
+        auto fits = [&](const Plan& q) {
+            const uint64_t spt = cl.cap / q.g.n_tiles;
+            const uint64_t tile_blocks_max = q.g.bpt < q.g.nbx ? q.g.bpt : q.g.nbx;
+            return reinterpret_cast<uintptr_t>(f.x_hat) % (4u * (uint32_t)q.V) == 0 && spt > 0 &&
+                   tile_blocks_max * bcells <= 2ull * spt;
+        };
+        while (!fits(pl)) {
+            if (pl.V == 1 || !finish_plan(p, pl.V / 2, pl)) return DQ_ENOTSUP;
+        }
+        L.plans[i] = pl;
+        const std::array<int, 3> key{pl.dim, pl.B, pl.V};
+        int c = -1;
+        for (size_t k = 0; k < L.classes.size(); ++k)
+            if (L.classes[k] == key) c = (int)k;
+        if (c < 0) {
+            c = (int)L.classes.size();
+            L.classes.push_back(key);
+        }
+        L.cls[i] = c;
+        const bool vec4 = (reinterpret_cast<uintptr_t>(f.x) & 15u) == 0;
+        aux_units += needs_range(*p) ? (uint64_t)minmax_parts(pl.g.N, vec4) : 1u;
+        chunk_units += (pl.g.n_tiles + kChunkTiles - 1) / kChunkTiles;
+        class_units += (pl.g.n_tiles + kUnitTiles - 1) / kUnitTiles;
+    }
+    if (aux_units > 0xffffffffull || chunk_units * kChunkSplit > 0xffffffffull || class_units > 0xffffffffull)
+        return DQ_ENOTSUP;
+    L.n_aux_units = (uint32_t)aux_units;
+    L.n_chunk_units = (uint32_t)chunk_units;
+    L.n_class_units = (uint32_t)class_units;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.enc = take(sizeof(EncArgs) * n);
+    L.dec = take(sizeof(DecArgs) * n);
+    L.aux = take(sizeof(AuxField) * n);
+    L.place = take(sizeof(PlaceField) * n);
+    L.aux_units = take(sizeof(uint2) * aux_units);
+    L.chunk_units = take(sizeof(uint2) * chunk_units);
+    L.class_units = take(2 * sizeof(uint4) * class_units);  // encode units, then decode units, class by class
+    L.tickets = take(sizeof(unsigned int) * 2 * L.classes.size());
+    L.total = off;
+    return DQ_OK;
+}
+
 }  // namespace
+
+extern "C" {
+
+dq_status dq_batch_persistent_workspace(const dq_batch_field* fields, uint64_t n, uint64_t* bytes) {
+    if (!bytes) return DQ_EINVAL;
+    PersistentLayout L;
+    const dq_status st = persistent_plan(fields, n, L);
+    if (st != DQ_OK) return st;
+    *bytes = L.total;
+    return DQ_OK;
+}
+
+dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, void* ws, uint64_t ws_bytes,
+                                     dq_batch_graph** graph) {
+    if (!graph) return DQ_EINVAL;
+    *graph = nullptr;
+    PersistentLayout L;
+    dq_status st = persistent_plan(fields, n, L);
+    if (st != DQ_OK) return st;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) || ws_bytes < L.total) return DQ_EINVAL;
+    char* w = static_cast<char*>(ws);
+    // the tables, built on the host
+    std::vector<EncArgs> enc(n);
+    std::vector<DecArgs> dec(n);
+    std::vector<AuxField> aux(n);
+    std::vector<PlaceField> place(n);
+    std::vector<uint2> aux_units, chunk_units;
+    std::vector<std::vector<uint4>> cunits(L.classes.size());
+    for (uint64_t i = 0; i < n; ++i) {
+        const dq_batch_field& f = fields[i];
+        const dq_params* p = &f.p;
+        const Plan& pl = L.plans[i];
+        const CompressLayout cl = compress_layout(p, f.out_cap);
+        char* cw = static_cast<char*>(f.cws);
+        Scalars* sc = reinterpret_cast<Scalars*>(cw + cl.sc);
+        uint32_t* tiles = reinterpret_cast<uint32_t*>(cw + cl.tiles);
+        uint32_t* toff = reinterpret_cast<uint32_t*>(cw + cl.toff);
+        uint32_t* csum = reinterpret_cast<uint32_t*>(cw + cl.csum);
+        uint32_t* info = reinterpret_cast<uint32_t*>(cw + cl.info);
+        uint2* parts = reinterpret_cast<uint2*>(cw + cl.parts);
+        Staging stg;
+        stg.spt = (uint32_t)(cl.cap / pl.g.n_tiles);
+        stg.region = reinterpret_cast<uint4*>(cw + cl.region);
+        stg.ovf = reinterpret_cast<uint4*>(cw + cl.ovf);
+        stg.ovf_cap = (uint32_t)cl.cap;
+        stg.bcells = (uint32_t)pl.B * (pl.dim >= 2 ? (uint32_t)pl.B : 1u) * (pl.dim == 3 ? (uint32_t)pl.B : 1u);
+        stg.dense = 1u;
+        const bool vec4 = (reinterpret_cast<uintptr_t>(f.x) & 15u) == 0;
+        const int nparts = needs_range(*p) ? minmax_parts(pl.g.N, vec4) : 0;
+        EncArgs& ea = enc[i];
+        ea.bound = BoundArgs{parts, nparts, p->eb, p->eb_mode == DQ_EB_REL ? 1 : 0};
+        ea.eb_out = &f.cres->eb_abs;
+        ea.x = f.x;
+        ea.codes = f.codes;
+        ea.pads = f.pads;
+        ea.block_info = info;
+        ea.tile_count = tiles;
+        ea.stg = stg;
+        ea.sc = sc;
+        ea.status = &f.cres->status;
+        ea.g = pl.g;
+        ea.R = p->radius;
+        ea.pad_mode = p->pad_mode;
+        DecArgs& da = dec[i];
+        da.src = reinterpret_cast<const ResultView*>(f.cres);
+        da.cap = (uint32_t)cl.cap;
+        da.res_word = reinterpret_cast<unsigned long long*>(f.dres);
+        da.n_out_out = reinterpret_cast<unsigned long long*>(&f.dres->n_out);
+        da.eb_out = &f.dres->eb_abs;
+        da.eb_abs = 1.0;
+        da.tag = next_tag();
+        da.codes = f.codes;
+        da.out_idx = f.out_idx;
+        da.out_val = f.out_val;
+        da.pads = f.pads;
+        da.block_start = nullptr;
+        da.tile_off = toff;
+        da.tile_count = tiles;
+        da.block_info = info;
+        da.x_hat = f.x_hat;
+        da.g = pl.g;
+        da.twoeb = 2.0;
+        da.n_out = 0;
+        da.R = p->radius;
+        da.pad_mode = p->pad_mode;
+        AuxField& af = aux[i];
+        af.x = f.x;
+        af.N = pl.g.N;
+        af.parts = parts;
+        af.sc = sc;
+        af.res_ = f.cres;
+        af.eb = p->eb;
+        af.nparts = nparts;
+        af.vec4 = vec4 ? 1 : 0;
+        af.dres_word = reinterpret_cast<unsigned long long*>(f.dres);
+        for (int k = 0; k < (af.nparts ? af.nparts : 1); ++k) aux_units.push_back(make_uint2((uint32_t)i, (uint32_t)k));
+        PlaceField& pf = place[i];
+        pf.stg = stg;
+        pf.res_ = f.cres;
+        pf.out_cap = f.out_cap;
+        pf.cnt = tiles;
+        pf.tile_off = toff;
+        pf.chunk_sum = csum;
+        pf.n_tiles = pl.g.n_tiles;
+        pf.n_chunks = (pl.g.n_tiles + kChunkTiles - 1) / kChunkTiles;
+        pf.block_info = info;
+        pf.g = pl.g;
+        pf.out_idx = f.out_idx;
+        pf.out_val = f.out_val;
+        for (uint32_t c = 0; c < pf.n_chunks; ++c) chunk_units.push_back(make_uint2((uint32_t)i, c));
+        for (uint32_t t = 0; t < pl.g.n_tiles; t += kUnitTiles)
+            cunits[L.cls[i]].push_back(make_uint4((uint32_t)i, t, std::min(kUnitTiles, pl.g.n_tiles - t), 0u));
+    }
+    // class units: encode units of every class, then the same again for decode
+    std::vector<uint4> all_units;
+    std::vector<uint64_t> class_first;
+    for (const auto& v : cunits) {
+        class_first.push_back(all_units.size());
+        all_units.insert(all_units.end(), v.begin(), v.end());
+    }
+    const uint64_t n_units = all_units.size();
+    all_units.insert(all_units.end(), all_units.begin(), all_units.begin() + (ptrdiff_t)n_units);
+    auto put = [&](uint64_t off, const void* src, uint64_t bytes) {
+        return bytes == 0 || hipMemcpy(w + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!put(L.enc, enc.data(), sizeof(EncArgs) * n) || !put(L.dec, dec.data(), sizeof(DecArgs) * n) ||
+        !put(L.aux, aux.data(), sizeof(AuxField) * n) || !put(L.place, place.data(), sizeof(PlaceField) * n) ||
+        !put(L.aux_units, aux_units.data(), sizeof(uint2) * aux_units.size()) ||
+        !put(L.chunk_units, chunk_units.data(), sizeof(uint2) * chunk_units.size()) ||
+        !put(L.class_units, all_units.data(), sizeof(uint4) * all_units.size()))
+        return DQ_EDEVICE;
+
+    dq_batch_graph* g = new dq_batch_graph();
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        release(g);
+        return DQ_EDEVICE;
+    }
+    g->streams.push_back(s);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        release(g);
+        return DQ_EDEVICE;
+    }
+    const uint32_t ncls = (uint32_t)L.classes.size();
+    unsigned int* tickets = reinterpret_cast<unsigned int*>(w + L.tickets);
+    const uint4* units = reinterpret_cast<const uint4*>(w + L.class_units);
+    auto queue = [&](uint32_t c, bool decode) {
+        BatchQueue q;
+        q.enc = reinterpret_cast<const EncArgs*>(w + L.enc);
+        q.dec = reinterpret_cast<const DecArgs*>(w + L.dec);
+        q.units = units + (decode ? n_units : 0) + class_first[c];
+        q.n_units = (uint32_t)cunits[c].size();
+        q.ticket = tickets + 2 * c + (decode ? 1 : 0);
+        return q;
+    };
+    launch_batch_aux(reinterpret_cast<const AuxField*>(w + L.aux), reinterpret_cast<const uint2*>(w + L.aux_units),
+                     L.n_aux_units, tickets, 2 * ncls, s);
+    for (uint32_t c = 0; c < ncls && st == DQ_OK; ++c) {
+        const BatchQueue q = queue(c, false);
+        if (!launch_encode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, s))
+            st = DQ_ENOTSUP;
+    }
+    launch_batch_place(reinterpret_cast<const PlaceField*>(w + L.place),
+                       reinterpret_cast<const uint2*>(w + L.chunk_units), L.n_chunk_units, s);
+    for (uint32_t c = 0; c < ncls && st == DQ_OK; ++c) {
+        const BatchQueue q = queue(c, true);
+        if (!launch_decode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, s))
+            st = DQ_ENOTSUP;
+    }
+    if (st == DQ_OK && hipGetLastError() != hipSuccess) st = DQ_EDEVICE;
+    hipGraph_t captured = nullptr;
+    const bool ended = hipStreamEndCapture(s, &captured) == hipSuccess;
+    g->graph = captured;
+    if (st == DQ_OK && !ended) st = DQ_EDEVICE;
+    if (st == DQ_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) st = DQ_EDEVICE;
+    if (st != DQ_OK) {
+        (void)hipGetLastError();
+        release(g);
+        return st;
+    }
+    *graph = g;
+    return DQ_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -48,10 +48,7 @@ struct DecState {
     __device__ __forceinline__ void init(const DecArgs& a, uint32_t blk, bool gvalid) {
         rank = 0;
         os = oe = 0;
-        if (a.n_out && gvalid) {
-            os = a.block_start[blk];
-            oe = a.block_start[blk + 1];
-        }
+        if (a.n_out && gvalid) block_run(a, blk, os, oe);
         peff = gvalid ? block_peff<DIM>(a, blk) : 0u;
 #pragma unroll
         for (int j = 0; j < V; ++j) pY[j] = 0;
@@ -306,12 +303,10 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
 }
 
 
+// Tile t of the call a, by one wave.
 template <int DIM, int B, int V>
-__global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
+__device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const int lane) {
     using C = Cfg<DIM, B, V>;
-    const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
-    const int lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * kWaves + wave;
     if (a.src) {  // the outlier count and bound of the compress call that wrote this stream
         const int sst = (int)uniform((uint32_t)a.src->status);
         const unsigned long long n = a.src->n_out;
@@ -332,7 +327,6 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
         *a.eb_out = a.eb_abs;
         status_init_tagged(a.res_word, a.tag);
     }
-    if (t >= a.g.n_tiles) return;
     const uint32_t tx = t % a.g.ntx;
     const uint32_t rr = t / a.g.ntx;
     const uint32_t by = rr % a.g.nby;
@@ -470,10 +464,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
             const uint32_t bx = tx * C::BPT + bi;
             if (bx >= a.g.nbx) break;
             uint32_t os = 0, oe = 0;
-            if (a.n_out) {
-                os = a.block_start[bx];
-                oe = a.block_start[bx + 1];
-            }
+            if (a.n_out) block_run(a, bx, os, oe);
             const uint32_t peff = block_peff<DIM>(a, bx);
             uint32_t rank = 0, carry = 0;
             for (int cb = 0; cb < C::NCH; cb += C::NBR) {
@@ -519,6 +510,32 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     if (ballot(corrupt) && lane == 0) status_corrupt_tagged(a.res_word, a.tag);
 }
 
+template <int DIM, int B, int V>
+__global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
+    const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * kWaves + wave;
+    if (t >= a.g.n_tiles) return;  // tile 0 (which initialises the result) always exists
+    decode_tile<DIM, B, V>(a, t, lane);
+}
+
+// Persistent decode of a batch of fields of one configuration, draining the
+// flattened (field, tile run) queue with an atomic ticket as the batch encode.
+template <int DIM, int B, int V>
+__global__ __launch_bounds__(kThreads) void k_decode_batch(BatchQueue q) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t u = 0;
+        if (lane == 0) u = __hip_atomic_fetch_add(q.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u = uniform(u);
+        if (u >= q.n_units) break;
+        const uint4 un = q.units[u];  // field, first tile, tiles
+        const DecArgs a = q.dec[uniform(un.x)];
+        const uint32_t t0 = uniform(un.y), t1 = t0 + uniform(un.z);
+        for (uint32_t t = t0; t < t1; ++t) decode_tile<DIM, B, V>(a, t, lane);
+    }
+}
+
 #ifndef DQ_DIM
 #error "dq_decode.hip is compiled once per DQ_DIM (1, 2, 3)"
 #endif
@@ -540,6 +557,34 @@ static bool try_launch_decode(int block, int v, const DecArgs& a, dim3 grid, hip
 
 bool DQ_CAT(launch_decode_dim, DQ_DIM)(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
     DQ_CONFIGS(DQ_DEC_CASE)
+    return false;
+}
+
+template <int D, int BB, int VV>
+static bool try_launch_decode_batch(int block, int v, const BatchQueue& q, int grid, hipStream_t stream) {
+    if constexpr (D == DQ_DIM) {
+        if (block == BB && v == VV) {
+            int per_cu = 0, dev = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(
+                    &k_decode_batch<D, BB, VV>), kThreads, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            const int resident = per_cu * cus;
+            hipLaunchKernelGGL((k_decode_batch<D, BB, VV>), dim3((uint32_t)(grid < resident ? grid : resident)),
+                               dim3(kThreads), 0, stream, q);
+            return true;
+        }
+    }
+    return false;
+}
+
+#define DQ_DECB_CASE(D, BB, VV) \
+    if (try_launch_decode_batch<D, BB, VV>(block, v, q, grid, stream)) return true;
+
+bool DQ_CAT(launch_decode_batch_dim, DQ_DIM)(int block, int v, const BatchQueue& q, int grid, hipStream_t stream) {
+    DQ_CONFIGS(DQ_DECB_CASE)
     return false;
 }
 

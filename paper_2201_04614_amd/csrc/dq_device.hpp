@@ -201,13 +201,44 @@ struct DecArgs {
     const uint32_t* out_idx;
     const int32_t* out_val;
     const int32_t* pads;
-    const uint32_t* block_start;  // n_blocks + 1 entries (unused when n_out == 0)
+    const uint32_t* block_start;  // n_blocks + 1 entries (unused when n_out == 0), or NULL:
+    // then the runs come from the compress call's tile offsets (tile_off),
+    // tile counts and in-tile block prefixes (block_info) - decoding in the
+    // same batch as the compress, with the compress call's tiling
+    const uint32_t* tile_off;
+    const uint32_t* tile_count;
+    const uint32_t* block_info;
     float* x_hat;
     Geom g;
     double twoeb;
     uint32_t n_out;
     int32_t R;
     int32_t pad_mode;
+};
+
+// First and one-past-last outlier of block blk.
+__device__ __forceinline__ void block_run(const DecArgs& a, uint32_t blk, uint32_t& os, uint32_t& oe) {
+    if (a.block_start) {
+        os = a.block_start[blk];
+        oe = a.block_start[blk + 1];
+        return;
+    }
+    const uint32_t bx = blk % a.g.nbx, row = blk / a.g.nbx;
+    const uint32_t t = row * a.g.ntx + bx / a.g.bpt;
+    const uint32_t base = a.tile_off[t];
+    os = base + (a.block_info[blk] & ~kOriginFlag);
+    const bool last = (bx + 1) % a.g.bpt == 0 || bx + 1 == a.g.nbx;
+    oe = base + (last ? a.tile_count[t] : (a.block_info[blk + 1] & ~kOriginFlag));
+}
+
+// Work queue of a persistent batch kernel: units of consecutive tiles of one
+// field, taken in ticket order; the arguments of every field of the batch.
+struct BatchQueue {
+    const EncArgs* enc;
+    const DecArgs* dec;
+    const uint4* units;  // (field, first tile, tiles, 0)
+    uint32_t n_units;
+    unsigned int* ticket;
 };
 
 // ------------------------------------------------------------------ lanes

@@ -402,31 +402,32 @@ __device__ __forceinline__ uint32_t enc_block_end(const EncArgs& a, EncState<DIM
     return step_total;
 }
 
-// One value per lane (V = 1) gives twice the tiles of V = 2; the register
-// budget is capped so that four waves fit on every SIMD.
-template <int DIM, int B, int V>
-__global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a) {
-    using C = Cfg<DIM, B, V>;
-    __shared__ uint4 sbuf_all[kWaves][kStageCap];
-    const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
-    const int lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * kWaves + wave;
-    if (t >= a.g.n_tiles) return;
-    // the bound: every wave reduces the value-range partials itself; the
-    // call's status is loaded together with the partials
+// The bound of the call a (reduced from the value-range partials by this
+// wave) and the call's status so far; the wave that encodes tile 0 reports
+// the bound and any bound error.
+__device__ __forceinline__ Bound encode_bound(const EncArgs& a, int& st_in, const int lane, const bool first) {
     uint4 pp[kBoundLoads];
     bound_fetch(a.bound, pp, lane);
-    const int st_in = __builtin_nontemporal_load(a.status);
-    WaveCtx w{sbuf_all[wave], 0u, 0u, t, lane, 0u};
+    st_in = __builtin_nontemporal_load(a.status);  // loaded together with the partials
+    const Bound bd = bound_finish(a.bound, pp, lane);
+    if (a.bound.nparts && first && lane == 0) {
+        *a.eb_out = bd.eb;
+        if (bd.status != ST_OK) __hip_atomic_store(a.status, bd.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return bd;
+}
+
+// Tile t of the call a, by one wave (sbuf: the wave's LDS staging buffer;
+// bd, st_in: from encode_bound).
+template <int DIM, int B, int V>
+__device__ __forceinline__ void encode_tile(const EncArgs& a, uint4* sbuf, const uint32_t t, const int lane,
+                                            const Bound& bd, const int st_in) {
+    using C = Cfg<DIM, B, V>;
+    WaveCtx w{sbuf, 0u, 0u, t, lane, 0u};
     double r = 0.0, twoeb = 0.0, eb = 0.0;
     uint32_t gpad = 0;
     // false (and the tile's count 0) when the call has already failed
     auto prologue = [&]() -> bool {
-        const Bound bd = bound_finish(a.bound, pp, lane);
-        if (a.bound.nparts && t == 0 && lane == 0) {
-            *a.eb_out = bd.eb;
-            if (bd.status != ST_OK) __hip_atomic_store(a.status, bd.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         if (bd.status != ST_OK || st_in != ST_OK) {
             if (lane == 0) a.tile_count[t] = 0;
             return false;
@@ -705,6 +706,44 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     if (bad && lane == 0) __hip_atomic_store(a.status, ST_ERANGE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One value per lane (V = 1) gives twice the tiles of V = 2; the register
+// budget is capped so that four waves fit on every SIMD.
+template <int DIM, int B, int V>
+__global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a) {
+    __shared__ uint4 sbuf_all[kWaves][kStageCap];
+    const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * kWaves + wave;
+    if (t >= a.g.n_tiles) return;
+    int st_in = 0;
+    const Bound bd = encode_bound(a, st_in, lane, t == 0);
+    encode_tile<DIM, B, V>(a, sbuf_all[wave], t, lane, bd, st_in);
+}
+
+// Persistent encode of a batch of fields of one configuration: every wave
+// takes the next unit of the flattened (field, tile run) queue with an atomic
+// ticket until the queue is drained (every wave reaches the exit test), and
+// encodes the unit's tiles with its field's arguments (loaded into scalar
+// registers, and the field's bound reduced, once per unit).
+template <int DIM, int B, int V>
+__global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode_batch(BatchQueue q) {
+    __shared__ uint4 sbuf_all[kWaves][kStageCap];
+    const int wave = (int)uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t u = 0;
+        if (lane == 0) u = __hip_atomic_fetch_add(q.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u = uniform(u);
+        if (u >= q.n_units) break;
+        const uint4 un = q.units[u];  // field, first tile, tiles
+        const EncArgs a = q.enc[uniform(un.x)];
+        const uint32_t t0 = uniform(un.y), t1 = t0 + uniform(un.z);
+        int st_in = 0;
+        const Bound bd = encode_bound(a, st_in, lane, t0 == 0);
+        for (uint32_t t = t0; t < t1; ++t) encode_tile<DIM, B, V>(a, sbuf_all[wave], t, lane, bd, st_in);
+    }
+}
+
 #ifndef DQ_DIM
 #error "dq_encode.hip is compiled once per DQ_DIM (1, 2, 3)"
 #endif
@@ -726,6 +765,34 @@ static bool try_launch_encode(int block, int v, const EncArgs& a, dim3 grid, hip
 
 bool DQ_CAT(launch_encode_dim, DQ_DIM)(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream) {
     DQ_CONFIGS(DQ_ENC_CASE)
+    return false;
+}
+
+template <int D, int BB, int VV>
+static bool try_launch_encode_batch(int block, int v, const BatchQueue& q, int grid, hipStream_t stream) {
+    if constexpr (D == DQ_DIM) {
+        if (block == BB && v == VV) {
+            int per_cu = 0, dev = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(
+                    &k_encode_batch<D, BB, VV>), kThreads, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            const int resident = per_cu * cus;
+            hipLaunchKernelGGL((k_encode_batch<D, BB, VV>), dim3((uint32_t)(grid < resident ? grid : resident)),
+                               dim3(kThreads), 0, stream, q);
+            return true;
+        }
+    }
+    return false;
+}
+
+#define DQ_ENCB_CASE(D, BB, VV) \
+    if (try_launch_encode_batch<D, BB, VV>(block, v, q, grid, stream)) return true;
+
+bool DQ_CAT(launch_encode_batch_dim, DQ_DIM)(int block, int v, const BatchQueue& q, int grid, hipStream_t stream) {
+    DQ_CONFIGS(DQ_ENCB_CASE)
     return false;
 }
 

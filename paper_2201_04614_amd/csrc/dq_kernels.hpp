@@ -100,4 +100,57 @@ void launch_index(const uint32_t* out_idx, uint32_t n_out, Geom g, int block_log
                   uint32_t cap = 0);
 void launch_result_reset(void* res, hipStream_t stream);
 
+// ---------------------------------------------------------------- batches
+
+// Per-field arguments of the batched value-range pass / bound record.
+struct AuxField {
+    const float* x;
+    uint64_t N;
+    uint2* parts;
+    Scalars* sc;
+    void* res_;       // the compress dq_result (device)
+    double eb;        // absolute bound (nparts == 0)
+    int nparts;       // 0: absolute bound, no value-range pass: initialisation only
+    int vec4;
+    unsigned long long* dres_word;  // the decompress result's status word
+};
+
+// Per-field arguments of the batched placement (dense staging).
+struct PlaceField {
+    Staging stg;
+    void* res_;
+    uint64_t out_cap;
+    const uint32_t* cnt;  // tile outlier counts
+    uint32_t* tile_off;
+    uint32_t* chunk_sum;
+    uint32_t n_tiles, n_chunks;
+    const uint32_t* block_info;
+    Geom g;
+    uint32_t* out_idx;
+    int32_t* out_val;
+};
+
+void launch_batch_aux(const AuxField* fields, const uint2* units, uint32_t n_units, unsigned int* tickets,
+                      uint32_t n_tickets, hipStream_t stream);
+void launch_batch_place(const PlaceField* fields, const uint2* units, uint32_t n_units, hipStream_t stream);
+
+// Persistent batch encode / decode of one (dim, block, v) class; grid =
+// min(units, resident workgroups). False if the class is not built.
+bool launch_encode_batch_dim1(int block, int v, const BatchQueue& q, int grid, hipStream_t stream);
+bool launch_encode_batch_dim2(int block, int v, const BatchQueue& q, int grid, hipStream_t stream);
+bool launch_encode_batch_dim3(int block, int v, const BatchQueue& q, int grid, hipStream_t stream);
+bool launch_decode_batch_dim1(int block, int v, const BatchQueue& q, int grid, hipStream_t stream);
+bool launch_decode_batch_dim2(int block, int v, const BatchQueue& q, int grid, hipStream_t stream);
+bool launch_decode_batch_dim3(int block, int v, const BatchQueue& q, int grid, hipStream_t stream);
+inline bool launch_encode_batch(int dim, int block, int v, const BatchQueue& q, int grid, hipStream_t stream) {
+    return dim == 1 ? launch_encode_batch_dim1(block, v, q, grid, stream)
+         : dim == 2 ? launch_encode_batch_dim2(block, v, q, grid, stream)
+         : dim == 3 ? launch_encode_batch_dim3(block, v, q, grid, stream) : false;
+}
+inline bool launch_decode_batch(int dim, int block, int v, const BatchQueue& q, int grid, hipStream_t stream) {
+    return dim == 1 ? launch_decode_batch_dim1(block, v, q, grid, stream)
+         : dim == 2 ? launch_decode_batch_dim2(block, v, q, grid, stream)
+         : dim == 3 ? launch_decode_batch_dim3(block, v, q, grid, stream) : false;
+}
+
 }  // namespace dq

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2201_04614_amd import binding as dq
@@ -131,3 +133,33 @@ def test_noalloc_refuses_oversized_calls_before_any_launch(L):
     bad = dq.make_params((256, 256, 256), 0.0, "rel", 8, "zero", 512)
     assert L.dq_compress_noalloc(C.byref(bad), fake, fake, fake, fake, 1, None, fake, None) == dq.DQ_EINVAL
     assert dq.compress_workspace(p, 1 << 20) <= dq.DQ_SCRATCH_BYTES
+
+
+def test_persistent_batch_refusals_on_the_host(L):
+    """dq_batch_persistent_workspace plans on the host: a global-mean field
+    (its own pass over q) or an outlier capacity below the cell count (dense
+    staging only) is DQ_ENOTSUP, a missing output DQ_EINVAL, before any
+    device call."""
+    from paper_2201_04614_amd import batch as BT
+    BT.lib()
+    fake = 1 << 24
+
+    def field(shape, pad="zero", cap=None, x_hat=True):
+        f = BT.Field()
+        f.p = dq.make_params(shape, 1e-3, "rel", 8, pad, 512)
+        n = int(np.prod(shape))
+        f.x = f.codes = f.out_idx = f.out_val = f.pads = f.cres = f.dres = fake
+        f.out_cap = n if cap is None else cap
+        f.cws = fake
+        f.cws_bytes = dq.compress_workspace(f.p, f.out_cap)
+        f.x_hat = fake if x_hat else None
+        return f
+
+    need = C.c_uint64(0)
+    for fields, want in (([field((64, 64, 64))], dq.DQ_OK),
+                         ([field((64, 64, 64)), field((100, 100), pad="global_mean")], dq.DQ_ENOTSUP),
+                         ([field((64, 64, 64), cap=1000)], dq.DQ_ENOTSUP),
+                         ([field((64, 64, 64), x_hat=False)], dq.DQ_EINVAL)):
+        arr = (BT.Field * len(fields))(*fields)
+        assert L.dq_batch_persistent_workspace(arr, len(fields), C.byref(need)) == want
+    assert need.value > 0

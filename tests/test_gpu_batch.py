@@ -84,43 +84,111 @@ def _batch_items():
     return items
 
 
-def _eager(x_dev, kw):
-    kw = dict(kw)
-    eb = kw.pop("eb")
-    cd = dq.Codec(tuple(x_dev.shape), eb, device=x_dev.device, **kw)
-    cd.compress_async(x_dev)
-    r = cd.result()
-    assert r.status == dq.DQ_OK, dq.strerror(r.status)
-    cd.decompress_async(r.eb_abs, int(r.n_out))  # the host-count path
-    return cd, r
+def _oracle(ref, x, kw):
+    """The oracle's stream and decoded field for one batch field."""
+    p = ref.params(x.shape, kw["eb"], kw["eb_mode"], kw["block"], kw["pad"], kw["radius"])
+    c = ref.compress(p, x, out_cap=x.size)
+    assert c.status == 0
+    st, xr = ref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads)
+    assert st == 0
+    return c, xr
 
 
-def test_batch_graph_replays_match_eager(ref):
+def _check_field(cd, c, xr, ctx):
+    """Every output of a batch field against the oracle: result, codes,
+    outlier indices and residuals, pads, decoded floats."""
+    r, rd = cd.result(), cd.decompress_result()
+    assert r.status == dq.DQ_OK and rd.status == dq.DQ_OK, (ctx, r.status, rd.status)
+    assert int(r.n_out) == c.n_out and r.eb_abs == c.eb_abs, ctx
+    assert int(rd.n_out) == c.n_out and rd.eb_abs == c.eb_abs, ctx
+    assert np.array_equal(cd.codes.cpu().numpy().view(np.uint16), c.codes), ctx
+    n = c.n_out
+    assert np.array_equal(cd.out_idx[:n].cpu().numpy().view(np.uint32), c.out_idx), ctx
+    assert np.array_equal(cd.out_val[:n].cpu().numpy(), c.out_val), ctx
+    npads = c.pads.size
+    assert np.array_equal(cd.pads[:npads].cpu().numpy(), c.pads.reshape(-1)), ctx
+    assert np.array_equal(cd.x_hat.cpu().numpy().view(np.uint32), xr.view(np.uint32)), ctx
+
+
+def _run_replays(ref, b, devs, items):
+    """Three launches of one graph; before the third, eager work changes one
+    input in place. Every field of every launch is checked against the oracle."""
     import torch
-    items = _batch_items()
-    devs = [(torch.from_numpy(x).cuda(), kw) for x, kw in items]
-    G.say(f"batch graph of {len(devs)} fields")
-    b = BT.Batch(devs, branches=4)
+    want = [_oracle(ref, x, kw) for x, kw in items]
     for rep in range(3):
-        if rep == 2:  # eager work between replays changes one input in place
+        if rep == 2:
             devs[3][0].mul_(1.5)
+            x3 = devs[3][0].cpu().numpy()
+            want[3] = _oracle(ref, x3, items[3][1])
         b.launch()
         torch.cuda.synchronize()
         for k, ((xd, kw), cd) in enumerate(zip(devs, b.codecs)):
-            r, rd = cd.result(), cd.decompress_result()
-            ecd, er = _eager(xd, kw)
-            erd = ecd.decompress_result()
-            ctx = f"replay {rep} field {k} {tuple(xd.shape)} {kw}"
-            assert r.status == er.status == dq.DQ_OK, ctx
-            assert int(r.n_out) == int(er.n_out) and r.eb_abs == er.eb_abs, ctx
-            assert rd.status == erd.status == dq.DQ_OK, ctx
-            assert torch.equal(cd.codes, ecd.codes), ctx
-            n = int(r.n_out)
-            assert torch.equal(cd.out_idx[:n], ecd.out_idx[:n]) and torch.equal(cd.out_val[:n], ecd.out_val[:n]), ctx
-            assert torch.equal(cd.x_hat.view(torch.int32), ecd.x_hat.view(torch.int32)), ctx
-            if k in (2, 5, 8):  # small fields: the oracle too
-                x = xd.cpu().numpy()
-                p = ref.params(x.shape, kw["eb"], kw["eb_mode"], kw["block"], kw["pad"], kw["radius"])
-                c = ref.compress(p, x)
-                assert c.n_out == n and np.array_equal(cd.codes.cpu().numpy().view(np.uint16), c.codes), ctx
+            _check_field(cd, *want[k], f"replay {rep} field {k} {tuple(xd.shape)} {kw}")
+
+
+def test_batch_graph_replays_match_oracle(ref):
+    import torch
+    items = _batch_items()
+    devs = [(torch.from_numpy(x.copy()).cuda(), kw) for x, kw in items]
+    G.say(f"batch graph of {len(devs)} fields")
+    b = BT.Batch(devs, branches=4)
+    _run_replays(ref, b, devs, items)
     b.close()
+
+
+def _persistent_items():
+    """The batch fields with paddings the persistent form takes (global
+    mean, which needs its own pass over q, swapped for the global max)."""
+    items = []
+    for x, kw in _batch_items():
+        kw = dict(kw)
+        if kw["pad"] == "global_mean":
+            kw["pad"] = "global_max"
+        items.append((x, kw))
+    return items
+
+
+def test_persistent_batch_replays_match_oracle(ref):
+    import torch
+    items = _persistent_items()
+    devs = [(torch.from_numpy(x.copy()).cuda(), kw) for x, kw in items]
+    G.say(f"persistent batch of {len(devs)} fields")
+    b = BT.PersistentBatch(devs)
+    _run_replays(ref, b, devs, items)
+    b.close()
+
+
+def test_persistent_batch_reports_field_errors(ref):
+    """A field that fails (non-finite input) reports ERANGE in both results
+    and leaves every other field of the launch exact."""
+    import torch
+    items = _persistent_items()[:6]
+    x_bad = items[1][0].copy()
+    x_bad[1000] = np.inf
+    items[1] = (x_bad, items[1][1])
+    devs = [(torch.from_numpy(x.copy()).cuda(), kw) for x, kw in items]
+    b = BT.PersistentBatch(devs)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, ((xd, kw), cd) in enumerate(zip(devs, b.codecs)):
+        if k == 1:
+            assert cd.result().status == dq.DQ_ERANGE and cd.decompress_result().status == dq.DQ_ERANGE
+            continue
+        _check_field(cd, *_oracle(ref, items[k][0], kw), f"field {k}")
+    b.close()
+
+
+def test_autotuner_choice_is_supported_and_exact(ref):
+    """The autotuner returns a block edge and width the kernels support for
+    the field's dimensionality, and the stream at that configuration is the
+    oracle's."""
+    import torch
+    from paper_2201_04614_amd import autotune as AT
+    for k, shape in enumerate([(300000,), (700, 900), (60, 70, 80)]):
+        x = F.power_law_grf(shape, slope=3.0, seed=60 + k)
+        xd = torch.from_numpy(x).cuda()
+        B, V, table = AT.tune(xd, 1e-3, "rel", frac=0.2, iters=2)
+        G.say(f"autotune {shape}: B={B} V={V}")
+        assert B in AT.BLOCKS[len(shape)] and V in AT.VECS and (B, V) in table
+        assert table[(B, V)] == min(table.values())
+        G.parity(ref, x, 1e-3, "rel", B, "zero", 512, vec=V)
