@@ -41,7 +41,7 @@ uint64_t cells(const dq_params& p) {
 using namespace dq;
 using namespace dq::host;
 
-constexpr uint32_t kUnitTiles = 4;  // tiles per ticket of the persistent encode / decode
+constexpr uint32_t kUnitTiles = 4 * kWaves;  // tiles per ticket (workgroup) of the persistent encode / decode
 
 // The queue and field tables of a persistent batch, in the caller's workspace.
 struct PersistentLayout {
@@ -274,18 +274,45 @@ dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, v
         !put(L.class_units, all_units.data(), sizeof(uint4) * all_units.size()))
         return DQ_EDEVICE;
 
+    // the classes' encode (and decode) kernels are independent: one graph
+    // branch per class, so one class's tail overlaps another's work
+    const uint32_t ncls = (uint32_t)L.classes.size();
     dq_batch_graph* g = new dq_batch_graph();
-    hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-        release(g);
-        return DQ_EDEVICE;
+    for (uint32_t k = 0; k <= ncls; ++k) {
+        hipStream_t bs;
+        if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
+            release(g);
+            return DQ_EDEVICE;
+        }
+        g->streams.push_back(bs);
     }
-    g->streams.push_back(s);
+    for (uint32_t k = 0; k < 2 * (ncls + 1); ++k) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            release(g);
+            return DQ_EDEVICE;
+        }
+        g->events.push_back(e);
+    }
+    hipStream_t s = g->streams[0];
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
         release(g);
         return DQ_EDEVICE;
     }
-    const uint32_t ncls = (uint32_t)L.classes.size();
+    // fork the class branches off s (events [phase * (ncls + 1)]), run f on
+    // branch c, join them back (events [phase * (ncls + 1) + 1 + c])
+    auto branches = [&](int phase, auto&& f) {
+        hipEvent_t fork = g->events[phase * (ncls + 1)];
+        bool ok = hipEventRecord(fork, s) == hipSuccess;
+        for (uint32_t c = 0; ok && c < ncls; ++c) {
+            hipStream_t bs = g->streams[1 + c];
+            ok = hipStreamWaitEvent(bs, fork, 0) == hipSuccess;
+            if (ok && !f(c, bs)) st = DQ_ENOTSUP;
+            hipEvent_t join = g->events[phase * (ncls + 1) + 1 + c];
+            ok = ok && hipEventRecord(join, bs) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
+        }
+        if (!ok && st == DQ_OK) st = DQ_EDEVICE;
+    };
     unsigned int* tickets = reinterpret_cast<unsigned int*>(w + L.tickets);
     const uint4* units = reinterpret_cast<const uint4*>(w + L.class_units);
     auto queue = [&](uint32_t c, bool decode) {
@@ -299,18 +326,16 @@ dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, v
     };
     launch_batch_aux(reinterpret_cast<const AuxField*>(w + L.aux), reinterpret_cast<const uint2*>(w + L.aux_units),
                      L.n_aux_units, tickets, 2 * ncls, s);
-    for (uint32_t c = 0; c < ncls && st == DQ_OK; ++c) {
+    branches(0, [&](uint32_t c, hipStream_t bs) {
         const BatchQueue q = queue(c, false);
-        if (!launch_encode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, s))
-            st = DQ_ENOTSUP;
-    }
+        return launch_encode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, bs);
+    });
     launch_batch_place(reinterpret_cast<const PlaceField*>(w + L.place),
                        reinterpret_cast<const uint2*>(w + L.chunk_units), L.n_chunk_units, s);
-    for (uint32_t c = 0; c < ncls && st == DQ_OK; ++c) {
+    branches(1, [&](uint32_t c, hipStream_t bs) {
         const BatchQueue q = queue(c, true);
-        if (!launch_decode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, s))
-            st = DQ_ENOTSUP;
-    }
+        return launch_decode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, bs);
+    });
     if (st == DQ_OK && hipGetLastError() != hipSuccess) st = DQ_EDEVICE;
     hipGraph_t captured = nullptr;
     const bool ended = hipStreamEndCapture(s, &captured) == hipSuccess;

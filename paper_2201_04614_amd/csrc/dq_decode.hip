@@ -520,19 +520,25 @@ __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
 }
 
 // Persistent decode of a batch of fields of one configuration, draining the
-// flattened (field, tile run) queue with an atomic ticket as the batch encode.
+// flattened (field, run of tiles) queue with a workgroup ticket as the batch
+// encode does.
 template <int DIM, int B, int V>
-__global__ __launch_bounds__(kThreads) void k_decode_batch(BatchQueue q) {
+__global__ __launch_bounds__(kThreads) void k_decode_batch(const DecArgs* __restrict__ dec,
+                                                           const uint4* __restrict__ units, uint32_t n_units,
+                                                           unsigned int* ticket) {
+    __shared__ uint32_t s_unit;
+    const int wave = (int)uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for (;;) {
-        uint32_t u = 0;
-        if (lane == 0) u = __hip_atomic_fetch_add(q.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        u = uniform(u);
-        if (u >= q.n_units) break;
-        const uint4 un = q.units[u];  // field, first tile, tiles
-        const DecArgs a = q.dec[uniform(un.x)];
+        if (threadIdx.x == 0) s_unit = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t u = uniform(s_unit);
+        __syncthreads();
+        if (u >= n_units) break;
+        const uint4 un = units[u];  // field, first tile, tiles
+        const DecArgs& a = dec[uniform(un.x)];
         const uint32_t t0 = uniform(un.y), t1 = t0 + uniform(un.z);
-        for (uint32_t t = t0; t < t1; ++t) decode_tile<DIM, B, V>(a, t, lane);
+        for (uint32_t t = t0 + (uint32_t)wave; t < t1; t += kWaves) decode_tile<DIM, B, V>(a, t, lane);
     }
 }
 
@@ -573,7 +579,7 @@ static bool try_launch_decode_batch(int block, int v, const BatchQueue& q, int g
                 cus = 256;
             const int resident = per_cu * cus;
             hipLaunchKernelGGL((k_decode_batch<D, BB, VV>), dim3((uint32_t)(grid < resident ? grid : resident)),
-                               dim3(kThreads), 0, stream, q);
+                               dim3(kThreads), 0, stream, q.dec, q.units, q.n_units, q.ticket);
             return true;
         }
     }

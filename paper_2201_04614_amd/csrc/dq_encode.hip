@@ -720,27 +720,39 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     encode_tile<DIM, B, V>(a, sbuf_all[wave], t, lane, bd, st_in);
 }
 
-// Persistent encode of a batch of fields of one configuration: every wave
-// takes the next unit of the flattened (field, tile run) queue with an atomic
-// ticket until the queue is drained (every wave reaches the exit test), and
-// encodes the unit's tiles with its field's arguments (loaded into scalar
-// registers, and the field's bound reduced, once per unit).
+// Persistent encode of a batch of fields of one configuration: every
+// workgroup takes the next unit of the flattened (field, run of tiles) queue
+// with an atomic ticket until the queue is drained (all waves of a workgroup
+// see the same ticket, so all reach the exit test together); its waves
+// encode the unit's tiles in turn, wave w the tiles t0 + w, t0 + w + 4, ...,
+// so the four waves work on adjacent tiles at a time, as in the per-call
+// kernel. The tables are restrict-qualified read-only kernel parameters, so
+// the compiler may load a field's arguments with scalar loads (and load them
+// again) instead of keeping them in vector registers; each wave reduces the
+// field's bound once per unit.
 template <int DIM, int B, int V>
-__global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode_batch(BatchQueue q) {
+__global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode_batch(const EncArgs* __restrict__ enc,
+                                                                             const uint4* __restrict__ units,
+                                                                             uint32_t n_units,
+                                                                             unsigned int* ticket) {
     __shared__ uint4 sbuf_all[kWaves][kStageCap];
+    __shared__ uint32_t s_unit;
     const int wave = (int)uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for (;;) {
-        uint32_t u = 0;
-        if (lane == 0) u = __hip_atomic_fetch_add(q.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        u = uniform(u);
-        if (u >= q.n_units) break;
-        const uint4 un = q.units[u];  // field, first tile, tiles
-        const EncArgs a = q.enc[uniform(un.x)];
+        if (threadIdx.x == 0) s_unit = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t u = uniform(s_unit);
+        __syncthreads();  // read by every wave before the next ticket replaces it
+        if (u >= n_units) break;
+        const uint4 un = units[u];  // field, first tile, tiles
+        const EncArgs& a = enc[uniform(un.x)];
         const uint32_t t0 = uniform(un.y), t1 = t0 + uniform(un.z);
+        if (t0 + (uint32_t)wave >= t1) continue;
         int st_in = 0;
-        const Bound bd = encode_bound(a, st_in, lane, t0 == 0);
-        for (uint32_t t = t0; t < t1; ++t) encode_tile<DIM, B, V>(a, sbuf_all[wave], t, lane, bd, st_in);
+        const Bound bd = encode_bound(a, st_in, lane, t0 + (uint32_t)wave == 0);
+        for (uint32_t t = t0 + (uint32_t)wave; t < t1; t += kWaves)
+            encode_tile<DIM, B, V>(a, sbuf_all[wave], t, lane, bd, st_in);
     }
 }
 
@@ -781,7 +793,7 @@ static bool try_launch_encode_batch(int block, int v, const BatchQueue& q, int g
                 cus = 256;
             const int resident = per_cu * cus;
             hipLaunchKernelGGL((k_encode_batch<D, BB, VV>), dim3((uint32_t)(grid < resident ? grid : resident)),
-                               dim3(kThreads), 0, stream, q);
+                               dim3(kThreads), 0, stream, q.enc, q.units, q.n_units, q.ticket);
             return true;
         }
     }
