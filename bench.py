@@ -1,27 +1,31 @@
 """Benchmark of the dual-quantisation hot path on one MI355X.
 
-Default workload (one step): the 256^3 fp32 Gaussian random field with a k^-3
-power spectrum (seed 2), relative error bound 1e-3, 8^3 blocks, radius 512,
-run through compress + decompress once per padding mode (zero, block mean,
-edge mean) - every stage of the path: value-range pass, prequantisation +
-Lorenzo + codes + outlier staging (bound resolved per wave), outlier
-placement, outlier index, prefix-sum decode + dequantisation.
+Default workload (one step): a batch of 64 fp32 fields of uneven shape
+(1-D 2^20..2^24 cells, 2-D up to 1800 x 3600, 3-D up to 512^3; k^-2..k^-4
+Gaussian random fields synthesised on the device, seed 3; relative bounds
+1e-5..1e-2 per field, radius 512, zero padding), compressed and decompressed
+by one graph launch - every stage of the path for every field: value-range
+pass, prequantisation + Lorenzo + codes + outlier staging, outlier
+placement, prefix-sum decode + dequantisation. Block edge and cells per lane
+come from the autotuner, one configuration per dimensionality. Both batch
+forms are timed (a graph replaying every field's own kernels, and the
+persistent kernels draining a (field, tile) queue); the faster one gives the
+step time. The line also carries the outlier counts of the 256^3 field per
+padding mode and, on the 512 x 1024 x 1024 sharp-feature field, the learned
+per-block padding against plain zero padding (--no-extras skips both).
 
---workload c1 / c5 measure the 512^2 sinusoid field (abs eb 1e-4 * range,
-16^2 blocks, zero padding) and the 512 x 1024 x 1024 sharp-feature field
-(abs eb 1e-4 * range, 8^3 blocks, zero padding) the same way. --workload c3
-measures a batch of 64 uneven fields run as one HIP graph launch (block edge
-and vector width per field from the autotuner).
+--workload c2 / c1 / c5 measure one field at a time: the 256^3 k^-3 field
+(rel eb 1e-3, 8^3 blocks, zero / block-mean / edge-mean padding), the 512^2
+sinusoid field and the 512 x 1024 x 1024 sharp-feature field (abs eb 1e-4 *
+range, zero padding); every call reads and writes its own buffers, rotating
+over enough sets that the working set (> 1 GiB) cannot stay in the 256 MB
+Infinity Cache.
 
-Every call reads and writes its own buffers: inputs and outputs rotate over
-enough distinct sets that the working set (> 1 GiB) cannot stay in the 256 MB
-Infinity Cache, so the figure is HBM throughput. Inputs are resident in HBM
-before the timed region.
-
-Prints one JSON line: value = (padding modes) * 4N bytes / step time (GB/s of
-fp32 input through compress + decompress), the roofline of the dominant
-kernel (timed with HIP events recorded around it), and the CPU oracle timed
-on a bounded sample.
+Inputs are resident in HBM before the timed region. Prints one JSON line:
+value = 4N bytes of fp32 input (every field, every padding mode) / step
+time, the roofline of the dominant kernel (HIP events recorded around it on
+its own stream, in a second pass of the same steps), and the CPU oracle
+timed on bounded samples at one thread and on every host core.
 """
 
 import argparse
@@ -55,7 +59,7 @@ WORKLOADS = {
     "c3": dict(batch=True, sets=1, pads=("zero",), radius=512,
                desc="64 fp32 fields of uneven shape (1-D 2^20..2^24, 2-D up to 1800x3600, 3-D up to 512^3; "
                     "k^-2..k^-4 Gaussian random fields, device synthesis, seed 3), rel eb 1e-5..1e-2 per field, "
-                    "radius 512, zero padding, block edge and vector width per field from the autotuner; "
+                    "radius 512, zero padding, block edge and cells per lane per dimensionality from the autotuner; "
                     "step = one graph launch compressing and decompressing every field"),
 }
 
@@ -155,12 +159,166 @@ def batch_specs(seed=3, n=64):
     return specs
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_batch(xs, specs, cfg, W, all_cells=1 << 28, one_cells=1 << 25):
+    """The oracle, as it stands, on bounded samples of the batch: the first
+    fields in batch order (all dimensionalities interleave) up to all_cells
+    cells on every host core, up to one_cells cells on one thread; each field
+    compressed and decompressed with its own bound, block and padding."""
+    from oracle import dqref
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+
+    def run(limit, nthreads):
+        host, n = [], 0
+        for x, s in zip(xs, specs):
+            if host and n + x.numel() > limit:
+                break
+            host.append((x.cpu().numpy(), s))
+            n += x.numel()
+        t0 = time.perf_counter()
+        for x, s in host:
+            B, _ = cfg[x.ndim]
+            p = dqref.params(x.shape, s["eb"], "rel", B, "zero", W["radius"])
+            c = dqref.compress(p, x, out_cap=x.size, nthreads=nthreads)
+            st, _ = dqref.decompress(p, c.eb_abs, c.codes, c.out_idx, c.out_val, c.pads, nthreads=nthreads)
+            assert c.status == 0 and st == 0
+        dt = time.perf_counter() - t0
+        return round(4.0 * n / dt / 1e9, 4), f"first {len(host)} fields of the batch, {n} cells, {dt:.1f} s wall"
+
+    v_all, s_all = run(all_cells, threads)
+    v_one, s_one = run(one_cells, 1)
+    return {"value": v_all, "unit": "GB/s", "cores": threads, "kind": "oracle", "sample": s_all,
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": v_one, "unit": "GB/s", "cores": 1, "sample": s_one}}
+
+
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_64fields_persistent_traffic.txt")
+
+
+def stored_batch_traffic(kernel):
+    """HBM bytes per launch of the named batch kernel (a line
+    "traffic_bytes_per_launch[<kernel>]: <bytes>") from the committed counter
+    reading, or None when it was taken on other kernel sources or does not
+    cover that kernel."""
+    try:
+        with open(BATCH_TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv[f"traffic_bytes_per_launch[{kernel}]"])
+    except (KeyError, ValueError):
+        return None
+
+
+def c2_outlier_counts(W):
+    """Outliers per padding mode on the 256^3 k^-3 field (seed 2) and on the
+    same field offset by two value ranges (rel eb 1e-3, 8^3 blocks, R 512)."""
+    import torch
+    from paper_2201_04614_amd import binding as dq
+    from paper_2201_04614_amd import fields
+    x = fields.power_law_grf((256, 256, 256), slope=3.0, seed=2)
+    out = {}
+    for name, xx in (("c2", x), ("c2_offset", (x + np.float32(2.0 * fields.field_range(x))).astype(np.float32))):
+        xd = torch.from_numpy(np.ascontiguousarray(xx)).cuda()
+        row = {}
+        for pad in ("zero", "block_mean", "edge_mean", "global_mean"):
+            cd = dq.Codec(xd.shape, 1e-3, "rel", 8, pad, 512, out_cap=xd.numel())
+            cd.compress_async(xd)
+            r = cd.result()
+            assert r.status == dq.DQ_OK
+            row[pad] = int(r.n_out)
+        out[name] = row
+    return out
+
+
+def c5_selector_report(n_train=2000, log=log):
+    """The 512 x 1024 x 1024 sharp-feature field (seed 5, eb 1e-4 * range,
+    8^3 blocks, R 512): plain zero padding against the learned per-block
+    padding (network trained here on exhaustive labels of n_train generated
+    64^3 fields with libdq's kernels, bf16 inference, given-pads stream),
+    with the exhaustive search's outliers as the reference; GPU times of
+    compress + decompress and of the learned selection."""
+    import torch
+    from paper_2201_04614_amd import binding as dq
+    from paper_2201_04614_amd import fields
+    from paper_2201_04614_amd import selector as SEL
+    from paper_2201_04614_amd import selector_eval as SE
+    t0 = time.perf_counter()
+    X, yp, yb = SE.collect(n_train, (64, 64, 64))
+    theta = SEL.train(X, yp, yb, epochs=6, batch=4096, lr=2e-3)
+    tb = SEL.to_bf16(theta)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, yp, yb
+    log(f"bench: selector trained on {n_train} fields in {t_train:.1f} s")
+    shape = (512, 1024, 1024)
+    x = fields.sharp_feature_field_device(shape, seed=5)
+    eb = 1e-4 * float(x.max().double() - x.min().double())
+    n = x.numel()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def timed(cd, reps=5):
+        ms = []
+        for _ in range(reps + 1):
+            ev[0].record()
+            cd.compress_async(x)
+            cd.decompress_dev_async()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        r, rd = cd.result(), cd.decompress_result()
+        assert r.status == dq.DQ_OK and rd.status == dq.DQ_OK
+        return float(np.median(ms[1:])), int(r.n_out)
+
+    zero = dq.Codec(shape, eb, "abs", 8, "zero", 512, out_cap=n // 8)
+    ms_zero, out_zero = timed(zero)
+    del zero
+    ev[2].record()
+    info = SEL.block_features(x, eb, 8, 512)
+    pads, _, _ = SEL.learned_pads(tb, info)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ms_select = ev[2].elapsed_time(ev[3])
+    learned = dq.Codec(shape, eb, "abs", 8, "given", 512, out_cap=n // 8)
+    learned.pads[:pads.numel()].copy_(pads)
+    ms_learned, out_learned = timed(learned)
+    st = info.stats_host()
+    fl = info.flags.cpu().numpy()
+    lab = info.label.cpu().numpy()
+    out_best = int(st["nonorig"].astype(np.int64).sum() + ((fl >> lab) & 1).astype(np.int64).sum())
+    del learned, info, x
+    torch.cuda.empty_cache()
+    red = out_zero - out_best
+    return {"workload": "512x1024x1024 sharp features (seed 5), eb 1e-4*range, 8^3 blocks, R 512",
+            "zero_pad": {"outliers": out_zero, "outlier_pct": round(100.0 * out_zero / n, 4),
+                         "ms": round(ms_zero, 4), "GBps": round(4.0 * n / (ms_zero * 1e-3) / 1e9, 1)},
+            "learned_pad": {"outliers": out_learned, "outlier_pct": round(100.0 * out_learned / n, 4),
+                            "ms": round(ms_learned, 4), "GBps": round(4.0 * n / (ms_learned * 1e-3) / 1e9, 1),
+                            "select_ms": round(ms_select, 4),
+                            "share_of_exhaustive_reduction": round((out_zero - out_learned) / red, 4) if red else 1.0},
+            "exhaustive_pad_outliers": out_best, "train_fields": n_train, "train_s": round(t_train, 1)}
+
+
 def run_batch(args, W):
-    """The batched workload: one graph launch = compress + decompress of every field."""
+    """The batched workload: one step = one graph launch compressing and
+    decompressing every field (the persistent form when faster)."""
     import torch
     from paper_2201_04614_amd import autotune as AT
     from paper_2201_04614_amd import batch as BT
-    from paper_2201_04614_amd import binding as dq
     from paper_2201_04614_amd import fields
 
     specs = batch_specs()
@@ -173,18 +331,15 @@ def run_batch(args, W):
             log(f"bench: {k + 1} fields synthesised")
     N = sum(x.numel() for x in xs)
     torch.cuda.synchronize()
-    log(f"bench: {N} cells; autotuning block edge and vector width per field")
+    log(f"bench: {N} cells; autotuning block edge and vector width per dimensionality")
     t0 = time.perf_counter()
-    tuned = []
-    for k, (x, s) in enumerate(zip(xs, specs)):
-        tuned.append(AT.tune(x, s["eb"], "rel", frac=0.1, iters=3)[:2])
-        if k % 16 == 15:
-            log(f"bench: {k + 1} fields tuned")
+    cfg, _ = AT.tune_batch(xs, [s["eb"] for s in specs], "rel", frac=0.1, iters=3)
     t_tune = time.perf_counter() - t0
+    log(f"bench: tuned {cfg} in {t_tune:.1f} s")
 
-    def items(cfg):
-        return [(x, dict(eb=s["eb"], eb_mode="rel", block=B, pad="zero", radius=W["radius"], out_cap=x.numel(),
-                         vec=V)) for x, s, (B, V) in zip(xs, specs, cfg)]
+    def items(c):
+        return [(x, dict(eb=s["eb"], eb_mode="rel", block=c[x.dim()][0], pad="zero", radius=W["radius"],
+                         out_cap=x.numel(), vec=c[x.dim()][1])) for x, s in zip(xs, specs)]
 
     def time_graph(b, steps, warmup):
         for _ in range(max(1, warmup)):
@@ -201,49 +356,86 @@ def run_batch(args, W):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
-    b = BT.Batch(items(tuned), branches=4)
-    ms = time_graph(b, args.steps, args.warmup)
-    res = b.results()
-    per_out = [int(r.n_out) for r, _ in res]
-    n_out = sum(per_out)
-    # the same calls enqueued one by one on one stream (no graph)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        for cd, (x, _) in zip(b.codecs, items(tuned)):
-            cd.compress_async(x)
-            cd.decompress_dev_async()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_eager = e0.elapsed_time(e1) / args.steps
+    # the graph of per-field launches
+    b = BT.Batch(items(cfg), branches=4)
+    ms_graph = time_graph(b, args.steps, args.warmup)
+    per_out = [int(r.n_out) for r, _ in b.results()]
     b.close()
     del b
-    default = [({1: 1024, 2: 16, 3: 8}[x.dim()], 0) for x in xs]
-    b0 = BT.Batch(items(default), branches=4)
-    ms_default = time_graph(b0, args.steps, args.warmup)
-    b0.close()
-    del b0
-    # algorithmic bytes: value-range pass 4N, encode 6N + 8 n_out, decode 6N + 8 n_out
+    torch.cuda.empty_cache()
+    # the persistent form, with events around the largest class's kernels
+    pb = BT.PersistentBatch(items(cfg), hooks=True)
+    ms_pers = time_graph(pb, args.steps, args.warmup)
+    assert [int(r.n_out) for r, _ in pb.results()] == per_out
+    # per-kernel durations: the same launches again, each followed by a read
+    # of the events (kept out of the step time)
+    enc_ms, dec_ms = [], []
+    for _ in range(args.steps):
+        pb.run()  # the graph's kernels on torch's stream, events around the largest class's
+        torch.cuda.synchronize()
+        enc_ms.append(pb.enc_hook.elapsed_ms())
+        dec_ms.append(pb.dec_hook.elapsed_ms())
+    plans = [(x.dim(), cd.block, v) for x, cd, v in zip(xs, pb.codecs, pb.field_vec)]
+    big = next(pl for pl, c in zip(plans, pb.field_class) if c == 0)  # the class the hooks time
+    pb.close()
+    del pb
+    torch.cuda.empty_cache()
+    ms_untuned = None
+    if not args.no_extras:
+        default = {1: (1024, 0), 2: (16, 0), 3: (8, 0)}
+        b0 = BT.PersistentBatch(items(default))
+        ms_untuned = time_graph(b0, args.steps, args.warmup)
+        b0.close()
+        del b0
+        torch.cuda.empty_cache()
+    n_out = sum(per_out)
+    ms = min(ms_graph, ms_pers)
+    # the largest class: its fields' algorithmic bytes per encode / decode launch
+    cells_of = {}
+    for (d, B, V), x in zip(plans, xs):
+        cells_of[(d, B, V)] = cells_of.get((d, B, V), 0) + x.numel()
+    big_bytes = sum(6.0 * x.numel() + 8.0 * o for pl, x, o in zip(plans, xs, per_out) if pl == big)
+    e_ms, d_ms = float(np.mean(enc_ms)), float(np.mean(dec_ms))
+    kname, kms = (f"k_encode_batch<{big[0]},{big[1]},{big[2]}>", e_ms) if e_ms >= d_ms else \
+        (f"k_decode_batch<{big[0]},{big[1]},{big[2]}>", d_ms)
+    achieved = big_bytes / (kms * 1e-3) / 1e9
+    # algorithmic bytes of the whole step: value range 4N, encode and decode 6N + 8 n_out each
     alg = 16.0 * N + 16.0 * n_out
     value = 4.0 * N / (ms * 1e-3) / 1e9
-    achieved = alg / (ms * 1e-3) / 1e9
     out = {
         "metric": "dual-quant compress+decompress GB/s on 1 MI355X; % HBM peak; outlier %",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+i32", "data": "synthetic",
         "config": {"workload": W["desc"], "fields": len(specs), "cells": N, "radius": W["radius"],
-                   "graph_branches": 4},
-        "roofline": {"bound": "hbm", "kernel": "whole batch graph (all kernels)", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None},
-        "outlier_pct": round(100.0 * n_out / N, 4),
-        "ms_per_step_untuned": round(ms_default, 4), "ms_per_step_no_graph": round(ms_eager, 4),
+                   "path": "persistent" if ms_pers <= ms_graph else "graph of per-field launches",
+                   "tuned": {str(d): list(c) for d, c in sorted(cfg.items())}},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": stored_batch_traffic(kname), "avg_kernel_ms": round(kms, 5),
+                     "kernel_cells": cells_of[big], "kernel_source_hash": kernel_source_hash()},
+        "outlier_pct": round(100.0 * n_out / N, 4), "n_out": n_out,
+        "step_algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+        "step_pct_hbm_peak": round(100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 2),
+        "ms_per_step_graph": round(ms_graph, 4), "ms_per_step_persistent": round(ms_pers, 4),
+        "ms_per_step_persistent_untuned": round(ms_untuned, 4) if ms_untuned else None,
+        "kernels_ms": {f"k_encode_batch<{big[0]},{big[1]},{big[2]}>": round(e_ms, 5),
+                       f"k_decode_batch<{big[0]},{big[1]},{big[2]}>": round(d_ms, 5)},
         "autotune_s": round(t_tune, 2),
-        "tuned": [{"shape": list(s["shape"]), "block": B, "vec": V, "eb_rel": round(s["eb"], 8),
-                   "slope": round(s["slope"], 3), "outlier_pct": round(100.0 * po / n, 3)}
-                  for s, (B, V), po, n in zip(specs, tuned, per_out, [x.numel() for x in xs])],
+        "fields": [{"shape": list(s["shape"]), "eb_rel": round(s["eb"], 8), "slope": round(s["slope"], 3),
+                    "outlier_pct": round(100.0 * po / x.numel(), 3)} for s, po, x in zip(specs, per_out, xs)],
     }
+    if not args.no_extras:
+        log("bench: 256^3 outlier counts")
+        out["c2_outliers"] = c2_outlier_counts(W)
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline_batch(xs, specs, {d: c for d, c in cfg.items()}, W)
+    del xs
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("bench: 512x1024x1024 field, learned padding against zero padding")
+        out["c5_learned_vs_zero"] = c5_selector_report()
     print(json.dumps(out), flush=True)
 
 
@@ -292,12 +484,15 @@ def entropy_report(codecs, pads, n_out, reps=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sets", type=int, default=0, help="rotating buffer sets per padding mode (0 = workload's)")
     ap.add_argument("--vec", type=int, default=0, help="cells per lane hint (0 = automatic)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batch workload: skip the untuned run, the 256^3 outlier counts and the learned-padding "
+                         "report on the 512x1024x1024 field")
     ap.add_argument("--entropy", action="store_true",
                     help="also time the Huffman stage on each mode's codes and report the compression ratio")
     ap.add_argument("--copy-only", action="store_true",

@@ -74,10 +74,21 @@ dq_status dq_batch_graph_create(const dq_batch_field *fields, uint64_t n, int br
  * dq_batch_persistent_workspace bytes, holding the queues and the fields'
  * arguments; written once here (synchronously), read by every launch, owned
  * by the caller and kept until dq_batch_graph_destroy. Launches of the same
- * graph must not overlap (they share the tickets in ws). */
+ * graph must not overlap (they share the tickets in ws).
+ * class_out / vec_out (host arrays of n, either may be NULL): each field's
+ * class (0 = the class with the most cells, the one dq_batch_persistent_run
+ * times) and cells per lane. */
 dq_status dq_batch_persistent_workspace(const dq_batch_field *fields, uint64_t n, uint64_t *bytes);
 dq_status dq_batch_persistent_create(const dq_batch_field *fields, uint64_t n, void *ws, uint64_t ws_bytes,
-                                     dq_batch_graph **graph);
+                                     int32_t *class_out, int32_t *vec_out, dq_batch_graph **graph);
+
+/* The kernels of a persistent batch enqueued directly on hip_stream, one
+ * after another (no graph, no branches; same results as a graph launch),
+ * with optional timing events recorded right before and after the encode
+ * (enc_hooks) and decode (dec_hooks) kernel of the class with the most
+ * cells. DQ_EINVAL for a graph not made by dq_batch_persistent_create. */
+dq_status dq_batch_persistent_run(dq_batch_graph *graph, void *hip_stream, const dq_hooks *enc_hooks,
+                                  const dq_hooks *dec_hooks);
 
 /* Enqueue one execution of the graph on hip_stream. Per-field outcomes land
  * in each field's cres / dres. */

@@ -33,8 +33,14 @@ def tune(x, eb, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, blocks
     import torch
     d = x.dim()
     eb_abs = float(eb)
-    if eb_mode == "rel":  # the bound of the whole field, not of the sample
-        eb_abs = float(eb) * float(x.max() - x.min())
+    if eb_mode == "rel":  # the bound of the whole field (resolved by the codec), not of the sample
+        c = dq.Codec(tuple(x.shape), eb, "rel", BLOCKS[d][0], "zero", radius, out_cap=0, device=x.device)
+        c.compress_async(x)
+        r = c.result()
+        if r.status not in (dq.DQ_OK, dq.DQ_ECAPACITY):
+            raise dq.DQError(r.status, "value range")
+        eb_abs = float(r.eb_abs)
+        del c
     table = {}
     for B in (blocks or BLOCKS[d]):
         xs = _sample(x, frac, B)
@@ -63,3 +69,25 @@ def tune(x, eb, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, blocks
             table[(B, V)] = float(np.mean(ms)) * x.numel() / xs.numel()  # scaled to the whole field
     best = min(table, key=table.get)
     return best[0], best[1], table
+
+
+def tune_batch(xs, ebs, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3):
+    """One (block, vec) per dimensionality for a batch of fields: each field's
+    configurations are timed as in tune() (scaled to the whole field) and the
+    per-dimensionality sums decide, so the batch has one persistent kernel
+    class per dimensionality. Returns {ndim: (block, vec)} and the per-field
+    tables."""
+    totals, tables = {}, []
+    for x, eb in zip(xs, ebs):
+        _, _, table = tune(x, eb, eb_mode, pad, radius, frac, iters)
+        tables.append(table)
+        acc = totals.setdefault(x.dim(), {})
+        for cfg, ms in table.items():
+            acc[cfg] = acc.get(cfg, 0.0) + ms
+    best = {}
+    for d, acc in totals.items():
+        n_fields = sum(1 for x in xs if x.dim() == d)
+        # configurations every field of the dimensionality could run
+        full = [cfg for cfg in acc if sum(1 for x, t in zip(xs, tables) if x.dim() == d and cfg in t) == n_fields]
+        best[d] = min(full or acc, key=acc.get)
+    return best, tables

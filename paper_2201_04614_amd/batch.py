@@ -20,7 +20,7 @@ from . import binding as dq
 
 # every function include/dq_batch.h declares
 EXPORTS = ["dq_batch_graph_create", "dq_batch_graph_launch", "dq_batch_graph_destroy",
-           "dq_batch_persistent_workspace", "dq_batch_persistent_create"]
+           "dq_batch_persistent_workspace", "dq_batch_persistent_create", "dq_batch_persistent_run"]
 
 
 class Field(C.Structure):
@@ -47,7 +47,9 @@ def lib():
         L.dq_batch_persistent_workspace.argtypes = [C.POINTER(Field), C.c_uint64, C.POINTER(C.c_uint64)]
         L.dq_batch_persistent_workspace.restype = C.c_int
         L.dq_batch_persistent_create.argtypes = [C.POINTER(Field), C.c_uint64, vp, C.c_uint64,
-                                                 C.POINTER(C.c_void_p)]
+                                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_void_p)]
+        L.dq_batch_persistent_run.argtypes = [vp, vp, C.POINTER(dq.Hooks), C.POINTER(dq.Hooks)]
+        L.dq_batch_persistent_run.restype = C.c_int
         L.dq_batch_persistent_create.restype = C.c_int
         _ready = True
     return L
@@ -111,11 +113,15 @@ class Batch:
 
 class PersistentBatch(Batch):
     """The same batch through dq_batch_persistent_create: every field needs
-    out_cap >= its cell count and a padding other than global_mean."""
+    out_cap >= its cell count and a padding other than global_mean.
+    run() enqueues the same kernels without the graph; with hooks=True it
+    records HIP events around the largest class's encode and decode kernels
+    (self.enc_hook, self.dec_hook)."""
 
-    def __init__(self, items):
-        import torch
+    def __init__(self, items, hooks=False):
         self.items = items
+        self.enc_hook = dq.Hook() if hooks else None
+        self.dec_hook = dq.Hook() if hooks else None
         self.codecs, self._fields = _fields(items, True)
         need = C.c_uint64(0)
         st = lib().dq_batch_persistent_workspace(self._fields, len(items), C.byref(need))
@@ -123,7 +129,26 @@ class PersistentBatch(Batch):
             raise dq.DQError(st, "dq_batch_persistent_workspace")
         self.ws = dq._aligned_bytes(int(need.value), items[0][0].device)
         h = C.c_void_p()
-        st = lib().dq_batch_persistent_create(self._fields, len(items), _p(self.ws), self.ws.numel(), C.byref(h))
+        cls = (C.c_int32 * len(items))()
+        vec = (C.c_int32 * len(items))()
+        st = lib().dq_batch_persistent_create(self._fields, len(items), _p(self.ws), self.ws.numel(), cls, vec,
+                                              C.byref(h))
         if st != dq.DQ_OK:
             raise dq.DQError(st, "dq_batch_persistent_create")
         self._h = h
+        self.field_class = list(cls)  # 0: the class with the most cells (timed by the hooks)
+        self.field_vec = list(vec)
+
+    def run(self, stream=None):
+        hk = self.enc_hook is not None
+        st = lib().dq_batch_persistent_run(self._h, dq._stream_handle(stream),
+                                           C.byref(self.enc_hook.struct) if hk else None,
+                                           C.byref(self.dec_hook.struct) if hk else None)
+        if st != dq.DQ_OK:
+            raise dq.DQError(st, "dq_batch_persistent_run")
+
+    def close(self):
+        super().close()
+        for hk in (self.enc_hook, self.dec_hook):
+            if hk:
+                hk.close()

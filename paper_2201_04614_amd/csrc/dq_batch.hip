@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <array>
 #include <numeric>
 #include <vector>
@@ -17,6 +18,9 @@ struct dq_batch_graph {
     hipGraphExec_t exec = nullptr;
     std::vector<hipStream_t> streams;  // [0] capture origin, then the branches
     std::vector<hipEvent_t> events;    // [0] fork, then one join per branch
+    // persistent batches: the launch sequence, enqueued on one stream
+    // (timing hooks around the largest class's kernels) or with branches
+    std::function<dq_status(hipStream_t, bool, const dq_hooks*, const dq_hooks*)> enqueue;
 };
 
 namespace {
@@ -155,7 +159,7 @@ dq_status dq_batch_persistent_workspace(const dq_batch_field* fields, uint64_t n
 }
 
 dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, void* ws, uint64_t ws_bytes,
-                                     dq_batch_graph** graph) {
+                                     int32_t* class_out, int32_t* vec_out, dq_batch_graph** graph) {
     if (!graph) return DQ_EINVAL;
     *graph = nullptr;
     PersistentLayout L;
@@ -294,49 +298,86 @@ dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, v
         }
         g->events.push_back(e);
     }
+    // the class with the most cells carries the timing hooks
+    std::vector<uint64_t> class_cells(ncls, 0);
+    for (uint64_t i = 0; i < n; ++i) class_cells[L.cls[i]] += L.plans[i].g.N;
+    const uint32_t big = (uint32_t)(std::max_element(class_cells.begin(), class_cells.end()) - class_cells.begin());
+    for (uint64_t i = 0; i < n; ++i) {  // the hooked class is reported as class 0
+        const uint32_t c = (uint32_t)L.cls[i];
+        if (class_out) class_out[i] = c == big ? 0 : (int32_t)(c < big ? c + 1 : c);
+        if (vec_out) vec_out[i] = L.plans[i].V;
+    }
+    std::vector<uint32_t> class_units(ncls);
+    for (uint32_t c = 0; c < ncls; ++c) class_units[c] = (uint32_t)cunits[c].size();
+    const std::vector<std::array<int, 3>> classes = L.classes;
+    const PersistentLayout lay = L;
+    // The launch sequence. branch = true: the classes' encode (and decode)
+    // kernels on parallel streams forked from s and joined back (the graph);
+    // false: everything on s in order, the hooks around the largest class.
+    g->enqueue = [g, w, lay, classes, class_first, class_units, n_units, ncls, big](
+                     hipStream_t s, bool branch, const dq_hooks* enc_hooks, const dq_hooks* dec_hooks) -> dq_status {
+        dq_status rst = DQ_OK;
+        unsigned int* tickets = reinterpret_cast<unsigned int*>(w + lay.tickets);
+        const uint4* units = reinterpret_cast<const uint4*>(w + lay.class_units);
+        auto queue = [&](uint32_t c, bool decode) {
+            BatchQueue q;
+            q.enc = reinterpret_cast<const EncArgs*>(w + lay.enc);
+            q.dec = reinterpret_cast<const DecArgs*>(w + lay.dec);
+            q.units = units + (decode ? n_units : 0) + class_first[c];
+            q.n_units = class_units[c];
+            q.ticket = tickets + 2 * c + (decode ? 1 : 0);
+            return q;
+        };
+        auto hook = [&](const dq_hooks* h, bool after, hipStream_t bs) {
+            void* e = h ? (after ? h->ev_after : h->ev_before) : nullptr;
+            if (e) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(e), bs);
+        };
+        // fork the class branches off s (events [phase * (ncls + 1)]), run f
+        // on branch c, join them back (events [phase * (ncls + 1) + 1 + c])
+        auto phase = [&](int ph, auto&& f) {
+            if (!branch) {
+                for (uint32_t c = 0; c < ncls; ++c)
+                    if (!f(c, s)) rst = DQ_ENOTSUP;
+                return;
+            }
+            hipEvent_t fork = g->events[ph * (ncls + 1)];
+            bool ok = hipEventRecord(fork, s) == hipSuccess;
+            for (uint32_t c = 0; ok && c < ncls; ++c) {
+                hipStream_t bs = g->streams[1 + c];
+                ok = hipStreamWaitEvent(bs, fork, 0) == hipSuccess;
+                if (ok && !f(c, bs)) rst = DQ_ENOTSUP;
+                hipEvent_t join = g->events[ph * (ncls + 1) + 1 + c];
+                ok = ok && hipEventRecord(join, bs) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
+            }
+            if (!ok && rst == DQ_OK) rst = DQ_EDEVICE;
+        };
+        launch_batch_aux(reinterpret_cast<const AuxField*>(w + lay.aux),
+                         reinterpret_cast<const uint2*>(w + lay.aux_units), lay.n_aux_units, tickets, 2 * ncls, s);
+        phase(0, [&](uint32_t c, hipStream_t bs) {
+            const BatchQueue q = queue(c, false);
+            if (c == big) hook(enc_hooks, false, bs);
+            const bool ok = launch_encode_batch(classes[c][0], classes[c][1], classes[c][2], q, (int)q.n_units, bs);
+            if (c == big) hook(enc_hooks, true, bs);
+            return ok;
+        });
+        launch_batch_place(reinterpret_cast<const PlaceField*>(w + lay.place),
+                           reinterpret_cast<const uint2*>(w + lay.chunk_units), lay.n_chunk_units, s);
+        phase(1, [&](uint32_t c, hipStream_t bs) {
+            const BatchQueue q = queue(c, true);
+            if (c == big) hook(dec_hooks, false, bs);
+            const bool ok = launch_decode_batch(classes[c][0], classes[c][1], classes[c][2], q, (int)q.n_units, bs);
+            if (c == big) hook(dec_hooks, true, bs);
+            return ok;
+        });
+        if (rst == DQ_OK && hipGetLastError() != hipSuccess) rst = DQ_EDEVICE;
+        return rst;
+    };
     hipStream_t s = g->streams[0];
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
         release(g);
         return DQ_EDEVICE;
     }
-    // fork the class branches off s (events [phase * (ncls + 1)]), run f on
-    // branch c, join them back (events [phase * (ncls + 1) + 1 + c])
-    auto branches = [&](int phase, auto&& f) {
-        hipEvent_t fork = g->events[phase * (ncls + 1)];
-        bool ok = hipEventRecord(fork, s) == hipSuccess;
-        for (uint32_t c = 0; ok && c < ncls; ++c) {
-            hipStream_t bs = g->streams[1 + c];
-            ok = hipStreamWaitEvent(bs, fork, 0) == hipSuccess;
-            if (ok && !f(c, bs)) st = DQ_ENOTSUP;
-            hipEvent_t join = g->events[phase * (ncls + 1) + 1 + c];
-            ok = ok && hipEventRecord(join, bs) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
-        }
-        if (!ok && st == DQ_OK) st = DQ_EDEVICE;
-    };
-    unsigned int* tickets = reinterpret_cast<unsigned int*>(w + L.tickets);
-    const uint4* units = reinterpret_cast<const uint4*>(w + L.class_units);
-    auto queue = [&](uint32_t c, bool decode) {
-        BatchQueue q;
-        q.enc = reinterpret_cast<const EncArgs*>(w + L.enc);
-        q.dec = reinterpret_cast<const DecArgs*>(w + L.dec);
-        q.units = units + (decode ? n_units : 0) + class_first[c];
-        q.n_units = (uint32_t)cunits[c].size();
-        q.ticket = tickets + 2 * c + (decode ? 1 : 0);
-        return q;
-    };
-    launch_batch_aux(reinterpret_cast<const AuxField*>(w + L.aux), reinterpret_cast<const uint2*>(w + L.aux_units),
-                     L.n_aux_units, tickets, 2 * ncls, s);
-    branches(0, [&](uint32_t c, hipStream_t bs) {
-        const BatchQueue q = queue(c, false);
-        return launch_encode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, bs);
-    });
-    launch_batch_place(reinterpret_cast<const PlaceField*>(w + L.place),
-                       reinterpret_cast<const uint2*>(w + L.chunk_units), L.n_chunk_units, s);
-    branches(1, [&](uint32_t c, hipStream_t bs) {
-        const BatchQueue q = queue(c, true);
-        return launch_decode_batch(L.classes[c][0], L.classes[c][1], L.classes[c][2], q, (int)q.n_units, bs);
-    });
-    if (st == DQ_OK && hipGetLastError() != hipSuccess) st = DQ_EDEVICE;
+    st = g->enqueue(s, true, nullptr, nullptr);
     hipGraph_t captured = nullptr;
     const bool ended = hipStreamEndCapture(s, &captured) == hipSuccess;
     g->graph = captured;
@@ -433,6 +474,12 @@ dq_status dq_batch_graph_launch(dq_batch_graph* graph, void* hip_stream) {
     if (!graph || !graph->exec) return DQ_EINVAL;
     return hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess ? DQ_OK
                                                                                                   : DQ_EDEVICE;
+}
+
+dq_status dq_batch_persistent_run(dq_batch_graph* graph, void* hip_stream, const dq_hooks* enc_hooks,
+                                  const dq_hooks* dec_hooks) {
+    if (!graph || !graph->enqueue) return DQ_EINVAL;
+    return graph->enqueue(reinterpret_cast<hipStream_t>(hip_stream), false, enc_hooks, dec_hooks);
 }
 
 dq_status dq_batch_graph_destroy(dq_batch_graph* graph) {

@@ -124,6 +124,7 @@ def _run_replays(ref, b, devs, items):
         torch.cuda.synchronize()
         for k, ((xd, kw), cd) in enumerate(zip(devs, b.codecs)):
             _check_field(cd, *want[k], f"replay {rep} field {k} {tuple(xd.shape)} {kw}")
+    return want
 
 
 def test_batch_graph_replays_match_oracle(ref):
@@ -153,8 +154,17 @@ def test_persistent_batch_replays_match_oracle(ref):
     items = _persistent_items()
     devs = [(torch.from_numpy(x.copy()).cuda(), kw) for x, kw in items]
     G.say(f"persistent batch of {len(devs)} fields")
-    b = BT.PersistentBatch(devs)
-    _run_replays(ref, b, devs, items)
+    b = BT.PersistentBatch(devs, hooks=True)
+    want = _run_replays(ref, b, devs, items)
+    # the same kernels without the graph, timed around the largest class
+    for cd in b.codecs:
+        cd.x_hat.fill_(0.0)
+    b.run()
+    torch.cuda.synchronize()
+    assert b.enc_hook.elapsed_ms() > 0 and b.dec_hook.elapsed_ms() > 0
+    for k, ((xd, kw), cd) in enumerate(zip(devs, b.codecs)):
+        _check_field(cd, *want[k], f"eager run field {k} {tuple(xd.shape)} {kw}")
+    assert b.field_class.count(0) >= 1
     b.close()
 
 
