@@ -286,21 +286,24 @@ def c5_selector_report(n_train=2000, log=log):
 
     zero = dq.Codec(shape, eb, "abs", 8, "zero", 512, out_cap=n // 8)
     ms_zero, out_zero = timed(zero)
-    del zero
     ev[2].record()
     info = SEL.block_features(x, eb, 8, 512)
     pads, _, _ = SEL.learned_pads(tb, info)
     ev[3].record()
     torch.cuda.synchronize()
     ms_select = ev[2].elapsed_time(ev[3])
+    # the exhaustive reference: per block the zero-pad outliers away from the
+    # origin plus the best candidate's origin (statistics given the zero-pad codes)
+    info_ex = SEL.block_features(x, eb, 8, 512, codes=zero.codes)
+    del zero
     learned = dq.Codec(shape, eb, "abs", 8, "given", 512, out_cap=n // 8)
     learned.pads[:pads.numel()].copy_(pads)
     ms_learned, out_learned = timed(learned)
-    st = info.stats_host()
-    fl = info.flags.cpu().numpy()
-    lab = info.label.cpu().numpy()
+    st = info_ex.stats_host()
+    fl = info_ex.flags.cpu().numpy()
+    lab = info_ex.label.cpu().numpy()
     out_best = int(st["nonorig"].astype(np.int64).sum() + ((fl >> lab) & 1).astype(np.int64).sum())
-    del learned, info, x
+    del learned, info, info_ex, x
     torch.cuda.empty_cache()
     red = out_zero - out_best
     return {"workload": "512x1024x1024 sharp features (seed 5), eb 1e-4*range, 8^3 blocks, R 512",

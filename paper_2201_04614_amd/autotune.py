@@ -71,12 +71,17 @@ def tune(x, eb, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, blocks
     return best[0], best[1], table
 
 
-def tune_batch(xs, ebs, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3):
+DEFAULT_BLOCK = {1: 1024, 2: 16, 3: 8}
+
+
+def tune_batch(xs, ebs, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, margin=0.05):
     """One (block, vec) per dimensionality for a batch of fields: each field's
     configurations are timed as in tune() (scaled to the whole field) and the
     per-dimensionality sums decide, so the batch has one persistent kernel
-    class per dimensionality. Returns {ndim: (block, vec)} and the per-field
-    tables."""
+    class per dimensionality. A configuration replaces the default block edge
+    (its fastest width) only when it is faster by more than `margin`, so
+    timing noise does not flip the choice from run to run. Returns
+    {ndim: (block, vec)} and the per-field tables."""
     totals, tables = {}, []
     for x, eb in zip(xs, ebs):
         _, _, table = tune(x, eb, eb_mode, pad, radius, frac, iters)
@@ -89,5 +94,12 @@ def tune_batch(xs, ebs, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3
         n_fields = sum(1 for x in xs if x.dim() == d)
         # configurations every field of the dimensionality could run
         full = [cfg for cfg in acc if sum(1 for x, t in zip(xs, tables) if x.dim() == d and cfg in t) == n_fields]
-        best[d] = min(full or acc, key=acc.get)
+        cands = full or list(acc)
+        pick = min(cands, key=acc.get)
+        dflt = [c for c in cands if c[0] == DEFAULT_BLOCK[d]]
+        if dflt:
+            base = min(dflt, key=acc.get)
+            if acc[pick] > (1.0 - margin) * acc[base]:
+                pick = base
+        best[d] = pick
     return best, tables

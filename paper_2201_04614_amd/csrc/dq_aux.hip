@@ -412,6 +412,24 @@ __global__ __launch_bounds__(kMinmaxThreads) void k_batch_aux(const AuxField* __
     minmax_part(f.x, f.N, f.parts, f.vec4, f.sc, res, un.y, (uint32_t)f.nparts);
 }
 
+// The value range of every field with a value-range pass reduced to one
+// (min key, max key) pair, so that each wave of the batch encode loads 16
+// bytes instead of every partial: one wave per field.
+__global__ __launch_bounds__(64) void k_batch_range(const AuxField* __restrict__ fields, uint2* __restrict__ reduced) {
+    const AuxField f = fields[blockIdx.x];
+    if (f.nparts == 0) return;
+    const int lane = threadIdx.x;
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    for (int i = lane; i < f.nparts; i += 64) {
+        const uint2 v = f.parts[i];
+        kmin = min(kmin, v.x);
+        kmax = max(kmax, v.y);
+    }
+    kmin = wave_min_u32(kmin);
+    kmax = wave_max_u32(kmax);
+    if (lane == 0) reduced[2 * blockIdx.x] = make_uint2(kmin, kmax);
+}
+
 // Outlier totals of every 256-tile chunk of every field: unit = (field, chunk).
 __global__ __launch_bounds__(256) void k_batch_chunk_sums(const PlaceField* __restrict__ fields,
                                                           const uint2* __restrict__ units) {
@@ -430,10 +448,11 @@ __global__ __launch_bounds__(256) void k_batch_scatter(const PlaceField* __restr
                        f.g, f.out_idx, f.out_val, un.y, blockIdx.x % kChunkSplit);
 }
 
-void launch_batch_aux(const AuxField* fields, const uint2* units, uint32_t n_units, unsigned int* tickets,
-                      uint32_t n_tickets, hipStream_t stream) {
+void launch_batch_aux(const AuxField* fields, uint32_t n_fields, const uint2* units, uint32_t n_units,
+                      unsigned int* tickets, uint32_t n_tickets, uint2* reduced, hipStream_t stream) {
     hipLaunchKernelGGL(k_batch_aux, dim3(n_units), dim3(kMinmaxThreads), 0, stream, fields, units, tickets,
                        n_tickets);
+    hipLaunchKernelGGL(k_batch_range, dim3(n_fields), dim3(64), 0, stream, fields, reduced);
 }
 
 void launch_batch_place(const PlaceField* fields, const uint2* units, uint32_t n_units, hipStream_t stream) {

@@ -49,7 +49,7 @@ constexpr uint32_t kUnitTiles = 4 * kWaves;  // tiles per ticket (workgroup) of 
 
 // The queue and field tables of a persistent batch, in the caller's workspace.
 struct PersistentLayout {
-    uint64_t enc, dec, aux, place, aux_units, chunk_units, class_units, tickets, total;
+    uint64_t enc, dec, aux, place, aux_units, chunk_units, class_units, tickets, reduced, total;
     uint32_t n_aux_units, n_chunk_units, n_class_units;
     std::vector<int> cls;                          // class of every field
     std::vector<std::array<int, 3>> classes;       // (dim, block, v)
@@ -141,6 +141,7 @@ dq_status persistent_plan(const dq_batch_field* fields, uint64_t n, PersistentLa
     L.chunk_units = take(sizeof(uint2) * chunk_units);
     L.class_units = take(2 * sizeof(uint4) * class_units);  // encode units, then decode units, class by class
     L.tickets = take(sizeof(unsigned int) * 2 * L.classes.size());
+    L.reduced = take(sizeof(uint4) * n);  // one 16-byte (min key, max key) slot per field
     L.total = off;
     return DQ_OK;
 }
@@ -196,7 +197,9 @@ dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, v
         const bool vec4 = (reinterpret_cast<uintptr_t>(f.x) & 15u) == 0;
         const int nparts = needs_range(*p) ? minmax_parts(pl.g.N, vec4) : 0;
         EncArgs& ea = enc[i];
-        ea.bound = BoundArgs{parts, nparts, p->eb, p->eb_mode == DQ_EB_REL ? 1 : 0};
+        // the encode reads the field's range as one pair, reduced after the value-range pass
+        const uint2* range = nparts ? reinterpret_cast<const uint2*>(w + L.reduced) + 2 * i : parts;
+        ea.bound = BoundArgs{range, nparts ? 1 : 0, p->eb, p->eb_mode == DQ_EB_REL ? 1 : 0};
         ea.eb_out = &f.cres->eb_abs;
         ea.x = f.x;
         ea.codes = f.codes;
@@ -314,7 +317,8 @@ dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, v
     // The launch sequence. branch = true: the classes' encode (and decode)
     // kernels on parallel streams forked from s and joined back (the graph);
     // false: everything on s in order, the hooks around the largest class.
-    g->enqueue = [g, w, lay, classes, class_first, class_units, n_units, ncls, big](
+    const uint32_t n_fields = (uint32_t)n;
+    g->enqueue = [g, w, lay, classes, class_first, class_units, n_units, ncls, big, n_fields](
                      hipStream_t s, bool branch, const dq_hooks* enc_hooks, const dq_hooks* dec_hooks) -> dq_status {
         dq_status rst = DQ_OK;
         unsigned int* tickets = reinterpret_cast<unsigned int*>(w + lay.tickets);
@@ -351,8 +355,9 @@ dq_status dq_batch_persistent_create(const dq_batch_field* fields, uint64_t n, v
             }
             if (!ok && rst == DQ_OK) rst = DQ_EDEVICE;
         };
-        launch_batch_aux(reinterpret_cast<const AuxField*>(w + lay.aux),
-                         reinterpret_cast<const uint2*>(w + lay.aux_units), lay.n_aux_units, tickets, 2 * ncls, s);
+        launch_batch_aux(reinterpret_cast<const AuxField*>(w + lay.aux), n_fields,
+                         reinterpret_cast<const uint2*>(w + lay.aux_units), lay.n_aux_units, tickets, 2 * ncls,
+                         reinterpret_cast<uint2*>(w + lay.reduced), s);
         phase(0, [&](uint32_t c, hipStream_t bs) {
             const BatchQueue q = queue(c, false);
             if (c == big) hook(enc_hooks, false, bs);

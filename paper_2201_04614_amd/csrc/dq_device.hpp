@@ -487,8 +487,14 @@ constexpr int kBoundLoads = kBoundParts / 128;
 // ignored); bound_finish waits.
 __device__ __forceinline__ void bound_fetch(const BoundArgs& b, uint4 (&pp)[kBoundLoads], int lane) {
     const uint4* p2 = reinterpret_cast<const uint4*>(b.parts);
+    if (b.nparts > 2) {
 #pragma unroll
-    for (int k = 0; k < kBoundLoads; ++k) pp[k] = p2[lane + 64 * k];
+        for (int k = 0; k < kBoundLoads; ++k) pp[k] = p2[lane + 64 * k];
+    } else {  // one pair (a batch's pre-reduced value range): one 16-byte load
+        pp[0] = p2[0];
+#pragma unroll
+        for (int k = 1; k < kBoundLoads; ++k) pp[k] = make_uint4(0u, 0u, 0u, 0u);
+    }
 }
 
 // The absolute bound, resolved for a relative one (Section II-B, value-range

@@ -130,8 +130,10 @@ struct PlaceField {
     int32_t* out_val;
 };
 
-void launch_batch_aux(const AuxField* fields, const uint2* units, uint32_t n_units, unsigned int* tickets,
-                      uint32_t n_tickets, hipStream_t stream);
+// Value-range passes of every field, then each field's range reduced to the
+// pair reduced[2 * field] (16-byte aligned slots, 2 uint2 per field).
+void launch_batch_aux(const AuxField* fields, uint32_t n_fields, const uint2* units, uint32_t n_units,
+                      unsigned int* tickets, uint32_t n_tickets, uint2* reduced, hipStream_t stream);
 void launch_batch_place(const PlaceField* fields, const uint2* units, uint32_t n_units, hipStream_t stream);
 
 // Persistent batch encode / decode of one (dim, block, v) class; grid =
