@@ -349,3 +349,30 @@ def forward_bf16_f32(theta, X):
     h1 = bf16_round(np.maximum(_f32_layer(x, P["W1"], P["b1"]), np.float32(0)))
     h2 = bf16_round(np.maximum(_f32_layer(h1, P["W2"], P["b2"]), np.float32(0)))
     return _f32_layer(h2, P["W3"], P["b3"])
+
+
+
+def super_vote(shape, base, logits):
+    """Edge index (0, 1, 2 for 4, 8, 16) of every super-block from the
+    block-size logits (outputs 5, 6, 7) of the blocks at edge `base`: each
+    super-block's logits summed in fp32 over its blocks in row-major order,
+    the largest sum, ties to the larger edge."""
+    logits = np.asarray(logits, dtype=np.float32)
+    nb = [(n + base - 1) // base for n in shape]
+    nsb = [(n + SUPER - 1) // SUPER for n in shape]
+    per = SUPER // base
+    out = []
+    for sc in itertools.product(*[range(k) for k in nsb]):
+        acc = np.zeros(3, dtype=np.float32)
+        ranges = [range(c * per, min(nb[a], (c + 1) * per)) for a, c in enumerate(sc)]
+        for bc in itertools.product(*ranges):
+            b = 0
+            for a in range(len(shape)):
+                b = b * nb[a] + bc[a]
+            acc = (acc + logits[b, N_PAD:N_OUT]).astype(np.float32)
+        best = 2
+        for i in (1, 0):
+            if acc[i] > acc[best]:
+                best = i
+        out.append(best)
+    return np.array(out, dtype=np.int64)

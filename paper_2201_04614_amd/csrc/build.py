@@ -21,6 +21,7 @@ LIB = os.path.join(PKG, "libdq.so")
 # once per dimensionality so their instantiations build in parallel
 UNITS = [("dq_api.hip", "dq_api.o", []), ("dq_aux.hip", "dq_aux.o", []), ("dq_select.hip", "dq_select.o", []),
                                                                           ("dq_batch.hip", "dq_batch.o", []),
+                                                                          ("dq_mixed.hip", "dq_mixed.o", []),
                                                                           ("dq_huffman.hip", "dq_huffman.o", [])] + [
     (f"dq_{k}.hip", f"dq_{k}_{d}d.o", [f"-DDQ_DIM={d}"]) for k in ("encode", "decode") for d in (1, 2, 3)]
 ARCH = os.environ.get("DQ_OFFLOAD_ARCH", "gfx950")

@@ -302,3 +302,40 @@ def learned_pads(theta_bf16, info, stream=None):
     """The network's padding choice for every block, as "given" pad values."""
     pc, bc, _ = infer(theta_bf16, info.feat, stream=stream)
     return gather_pads(info, pc, stream), pc, bc
+
+
+# ------------------------------------------------------------------ mixed-edge streams
+
+def mixed_exhaustive(x_dev, eb, eb_mode, radius, stream=None):
+    """Exhaustive choice for a mixed stream: every super-block's edge with the
+    lowest side cost (the search's super-block labels, taken by libdq's
+    dq_super_label) and every block's best candidate at that edge. Returns
+    (edges, pads in stream order, pad_off, search)."""
+    from . import mixed as MX
+    shape = tuple(x_dev.shape)
+    s = exhaustive_search(x_dev, eb, eb_mode, radius, stream=stream)
+    edges, _ = MX.super_label(shape, s.super_cost, stream)
+    pad_off, _ = MX.pad_offsets(shape, edges, stream)
+    by_edge = {B: gather_pads(s.infos[B], s.infos[B].label, stream) for B in BSIZES}
+    n_pads = int(pad_off[-1].item())
+    return edges, MX.gather_pads(shape, edges, pad_off, by_edge, n_pads, stream), pad_off, s
+
+
+def mixed_learned(theta_bf16, x_dev, eb_abs, radius, base=8, stream=None):
+    """The network's choice for a mixed stream: the block-size head's logits
+    at edge `base` voted per super-block (dq_super_vote), the padding head
+    per block at every edge. Returns (edges, pads in stream order, pad_off)."""
+    from . import mixed as MX
+    shape = tuple(x_dev.shape)
+    by_edge = {}
+    logits_base = None
+    for B in BSIZES:
+        info = block_features(x_dev, eb_abs, B, radius, stream=stream)
+        pc, _, lg = infer(theta_bf16, info.feat, logits=B == base, stream=stream)
+        by_edge[B] = gather_pads(info, pc, stream)
+        if B == base:
+            logits_base = lg
+    edges, _ = MX.super_vote(shape, base, logits_base, stream)
+    pad_off, _ = MX.pad_offsets(shape, edges, stream)
+    n_pads = int(pad_off[-1].item())
+    return edges, MX.gather_pads(shape, edges, pad_off, by_edge, n_pads, stream), pad_off

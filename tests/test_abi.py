@@ -37,8 +37,9 @@ def declared_functions():
 def test_header_lists_every_export():
     from paper_2201_04614_amd import batch as BT
     from paper_2201_04614_amd import huffman as HF
+    from paper_2201_04614_amd import mixed as MX
     from paper_2201_04614_amd import selector as SEL
-    assert declared_functions() == sorted(dq.EXPORTS + SEL.EXPORTS + BT.EXPORTS + HF.EXPORTS)
+    assert declared_functions() == sorted(dq.EXPORTS + SEL.EXPORTS + BT.EXPORTS + HF.EXPORTS + MX.EXPORTS)
 
 
 def test_library_exports_every_declared_symbol(L):
