@@ -245,16 +245,10 @@ def c2_outlier_counts(W):
     return out
 
 
-def c5_selector_report(n_train=2000, log=log):
-    """The 512 x 1024 x 1024 sharp-feature field (seed 5, eb 1e-4 * range,
-    8^3 blocks, R 512): plain zero padding against the learned per-block
-    padding (network trained here on exhaustive labels of n_train generated
-    64^3 fields with libdq's kernels, bf16 inference, given-pads stream),
-    with the exhaustive search's outliers as the reference; GPU times of
-    compress + decompress and of the learned selection."""
+def train_selector(n_train=2000, log=log):
+    """The selector network trained on the GPU with libdq's kernels on the
+    exhaustive labels of n_train generated 64^3 fields (bf16 for inference)."""
     import torch
-    from paper_2201_04614_amd import binding as dq
-    from paper_2201_04614_amd import fields
     from paper_2201_04614_amd import selector as SEL
     from paper_2201_04614_amd import selector_eval as SE
     t0 = time.perf_counter()
@@ -265,6 +259,84 @@ def c5_selector_report(n_train=2000, log=log):
     t_train = time.perf_counter() - t0
     del X, yp, yb
     log(f"bench: selector trained on {n_train} fields in {t_train:.1f} s")
+    return tb, n_train, t_train
+
+
+def c4_mixed_report(tb, log=log):
+    """Held-out 512^3 fields, rel eb 1e-3: plain zero padding (8^3 blocks)
+    against mixed-edge streams (an edge in {4, 8, 16} per 16^3 super-block
+    and a padding per block) chosen by the exhaustive search and by the
+    network; outliers, side bytes (8 per outlier + 4 per pad + 1 per edge),
+    GPU times, and every mixed stream decoded and compared bit for bit with
+    the zero-padding stream's x_hat (the same q, so the same floats)."""
+    import torch
+    from paper_2201_04614_amd import binding as dq
+    from paper_2201_04614_amd import mixed as MX
+    from paper_2201_04614_amd import selector as SEL
+    from paper_2201_04614_amd import selector_eval as SE
+    shape = (512, 512, 512)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def gpu_ms(f):
+        torch.cuda.synchronize()
+        ev[0].record()
+        r = f()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return r, ev[0].elapsed_time(ev[1])
+
+    out = []
+    for name, kw, R in (("k^-3 + ramp + offset", dict(seed=7, planes=0, ramp_amp=8.0, offset=2.0), 64),
+                        ("sharp features", dict(seed=5, planes=25, ramp_amp=0.0, offset=0.0), 32)):
+        x, _, _ = SE._field(shape, **kw)
+        eb = SEL.resolve_eb(x, 1e-3, "rel")
+        n = x.numel()
+        ns = MX.num_super(shape)
+        zero = dq.Codec(shape, eb, "abs", 8, "zero", R, out_cap=n)
+        zero.compress_async(x)
+        zx = zero.decompress_dev_async()
+        rz = zero.result()
+        assert rz.status == dq.DQ_OK
+        row = {"field": name, "radius": R, "eb_abs": eb,
+               "zero_pad": {"outliers": int(rz.n_out), "side_bytes": 8 * int(rz.n_out)}}
+        zero_side = 8 * int(rz.n_out)
+        for kind in ("exhaustive", "learned"):
+            if kind == "exhaustive":
+                (edges, pads, off, _), ms_sel = gpu_ms(lambda: SEL.mixed_exhaustive(x, eb, "abs", R))
+            else:
+                (edges, pads, off), ms_sel = gpu_ms(lambda: SEL.mixed_learned(tb, x, eb, R))
+            st, ms_c = gpu_ms(lambda: MX.compress(x, eb, R, edges, pads, pad_off=off))
+            assert st.status == dq.DQ_OK
+            xh, ms_d = gpu_ms(lambda: MX.decompress(st))
+            n_pads = int(off[-1].item())
+            side = 8 * st.n_out + 4 * n_pads + ns
+            share = {int(E): round(float((edges == E).float().mean()), 4) for E in (4, 8, 16)}
+            row[kind] = {"outliers": st.n_out, "pads": n_pads, "side_bytes": side, "edge_share": share,
+                         "select_ms": round(ms_sel, 2), "compress_ms": round(ms_c, 3), "decompress_ms": round(ms_d, 3),
+                         "decoded_equals_zero_pad_x_hat": bool(torch.equal(xh.view(torch.int32),
+                                                                           zx.view(torch.int32)))}
+            del st, xh, edges, pads, off
+        ex_side = row["exhaustive"]["side_bytes"]
+        red = zero_side - ex_side
+        row["learned"]["share_of_exhaustive_side_byte_reduction"] = \
+            round((zero_side - row["learned"]["side_bytes"]) / red, 4) if red else 1.0
+        log(f"bench: c4 {name}: {json.dumps(row)}")
+        out.append(row)
+        del x, zero, zx
+        torch.cuda.empty_cache()
+    return out
+
+
+def c5_selector_report(tb, n_train, t_train, log=log):
+    """The 512 x 1024 x 1024 sharp-feature field (seed 5, eb 1e-4 * range,
+    8^3 blocks, R 512): plain zero padding against the learned per-block
+    padding (bf16 inference, given-pads stream), with the exhaustive
+    search's outliers as the reference; GPU times of compress + decompress
+    and of the learned selection."""
+    import torch
+    from paper_2201_04614_amd import binding as dq
+    from paper_2201_04614_amd import fields
+    from paper_2201_04614_amd import selector as SEL
     shape = (512, 1024, 1024)
     x = fields.sharp_feature_field_device(shape, seed=5)
     eb = 1e-4 * float(x.max().double() - x.min().double())
@@ -437,8 +509,11 @@ def run_batch(args, W):
     del xs
     torch.cuda.empty_cache()
     if not args.no_extras:
+        tb, n_train, t_train = train_selector()
+        log("bench: 512^3 fields, mixed-edge streams (exhaustive, learned) against zero padding")
+        out["c4_mixed_edges"] = c4_mixed_report(tb)
         log("bench: 512x1024x1024 field, learned padding against zero padding")
-        out["c5_learned_vs_zero"] = c5_selector_report()
+        out["c5_learned_vs_zero"] = c5_selector_report(tb, n_train, t_train)
     print(json.dumps(out), flush=True)
 
 
