@@ -74,7 +74,7 @@ def tune(x, eb, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, blocks
 DEFAULT_BLOCK = {1: 1024, 2: 16, 3: 8}
 
 
-def tune_batch(xs, ebs, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, margin=0.05):
+def tune_batch(xs, ebs, eb_mode="rel", pad="zero", radius=512, frac=0.1, iters=3, margin=0.10):
     """One (block, vec) per dimensionality for a batch of fields: each field's
     configurations are timed as in tune() (scaled to the whole field) and the
     per-dimensionality sums decide, so the batch has one persistent kernel
