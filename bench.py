@@ -408,7 +408,10 @@ def run_batch(args, W):
     torch.cuda.synchronize()
     log(f"bench: {N} cells; autotuning block edge and vector width per dimensionality")
     t0 = time.perf_counter()
-    cfg, _ = AT.tune_batch(xs, [s["eb"] for s in specs], "rel", frac=0.1, iters=3)
+    if args.batch_config:
+        cfg = {int(d): (int(b), int(v)) for d, b, v in (c.split(":") for c in args.batch_config.split(","))}
+    else:
+        cfg, _ = AT.tune_batch(xs, [s["eb"] for s in specs], "rel", frac=0.1, iters=3)
     t_tune = time.perf_counter() - t0
     log(f"bench: tuned {cfg} in {t_tune:.1f} s")
 
@@ -568,6 +571,9 @@ def main():
     ap.add_argument("--vec", type=int, default=0, help="cells per lane hint (0 = automatic)")
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-config", default="",
+                    help="batch workload: fixed block edge and cells per lane per dimensionality instead of the "
+                         "autotuner's, e.g. 1:1024:4,2:16:1,3:4:1 (to profile the configuration a run chose)")
     ap.add_argument("--no-extras", action="store_true",
                     help="batch workload: skip the untuned run, the 256^3 outlier counts and the learned-padding "
                          "report on the 512x1024x1024 field")
