@@ -58,14 +58,14 @@ struct DecState {
             for (int j = 0; j < V; ++j) pZ[k][j] = 0;
     }
 
-    // Load the window; every lane's block is valid and lane 63 holds the
-    // wave's last block (blocks in lane order), so the wave's outliers are
-    // entries os(lane 0) .. oe(lane 63). Block starts lie in [0, n_out] but
+    // Load the window; lanes 0 .. last hold valid blocks in lane order (lane
+    // last in the wave's last valid block), so the wave's outliers are
+    // entries os(lane 0) .. oe(lane last). Block starts lie in [0, n_out] but
     // need not increase over a list out of order (whose call ends in
     // ECORRUPT): an empty window then, never a wrapped count.
-    __device__ __forceinline__ void prefetch(const DecArgs& a, int lane) {
+    __device__ __forceinline__ void prefetch(const DecArgs& a, int lane, int last = 63) {
         win.base = uniform(os);
-        const uint32_t e63 = readlane(oe, 63);
+        const uint32_t e63 = readlane(oe, last);
         win.cnt = e63 > win.base ? min(e63 - win.base, 64u) : 0u;
         if (win.cnt) {
             const uint32_t k = win.base + min((uint32_t)lane, win.cnt - 1u);
@@ -361,47 +361,71 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
                     if (leader && gvalid && st.rank != st.oe - st.os) corrupt = true;
                 }
             }
-        } else if (C::NBT * C::NBR <= kMaxUnrollRows && (tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny &&
-                   (bz + 1) * C::BZ <= nz && (uint64_t)((C::BZ - 1) * ny + C::BY) * nx * 4u < 0x7fffffffull) {
-            // Interior tile: the block row is one straight-line sequence of
+        } else if (C::NBT * C::NBR <= kMaxUnrollRows && (uint64_t)((C::BZ - 1) * ny + C::BY) * nx * 4u < 0x7fffffffull) {
+            // Pipelined tile: the block row is one straight-line sequence of
             // NBT batches with kPipeDepth batches of loads in flight ahead of
-            // the one being decoded; loads and stores are unconditional and
-            // addressed from wave-uniform row bases.
+            // the one being decoded. Interior tiles (FULL) load and store
+            // unconditionally from wave-uniform row bases; a tile that reaches
+            // past the field's end loads clamped columns, rows and planes
+            // (always in bounds), stores under per-lane conditions and skips
+            // the batches of planes past the end.
             constexpr int NBT = C::NBT;
             constexpr int D = cmin(NBT, kPipeDepth);
             constexpr int YB = C::BY / C::NBR;  // batches per plane
             const uint32_t voff = (uint32_t)lane * V;
-            for (int ch = 0; ch < C::XCH; ++ch) {
-                const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
-                const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
-                const uint32_t x0 = bx0 * B + voff;
-                const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
-                const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
-                const Rsrc crs = make_rsrc(a.codes + base);
-                const Rsrc ors = make_rsrc(a.x_hat + base);
-                DecState<DIM, B, V> st;
-                st.init(a, blk, true);
-                uint32_t buf[D][C::NBR][V];
-                auto load = [&](auto bI, uint32_t (&bb)[C::NBR][V]) {
-                    constexpr int b = decltype(bI)::value;
-                    const uint32_t row0 = ((uint32_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
+            auto run = [&](auto fullI) {
+                constexpr bool FULL = decltype(fullI)::value != 0;
+                const uint32_t zmax = FULL ? (uint32_t)C::BZ - 1u : min((uint32_t)C::BZ, nz - bz * C::BZ) - 1u;
+                const uint32_t ymax = FULL ? (uint32_t)C::BY - 1u : min((uint32_t)C::BY, ny - by * C::BY) - 1u;
+                for (int ch = 0; ch < C::XCH; ++ch) {
+                    const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
+                    if (!FULL && bx0 >= a.g.nbx) break;  // uniform
+                    const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                    const bool gvalid = FULL || bx < a.g.nbx;
+                    const uint32_t x0 = bx0 * B + voff;
+                    const bool xin = FULL || x0 < nx;
+                    // nx is a multiple of V: the clamped offset is >= 0
+                    const uint32_t lvoff = FULL ? voff : min(x0, nx - V) - bx0 * B;
+                    const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
+                    const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
+                    const Rsrc crs = make_rsrc(a.codes + base);
+                    const Rsrc ors = make_rsrc(a.x_hat + base);
+                    DecState<DIM, B, V> st;
+                    st.init(a, blk, gvalid);
+                    uint32_t buf[D][C::NBR][V];
+                    auto load = [&](auto bI, uint32_t (&bb)[C::NBR][V]) {
+                        constexpr int b = decltype(bI)::value;
+                        const uint32_t zc = FULL ? (uint32_t)(b / YB) : min((uint32_t)(b / YB), zmax);
 #pragma unroll
-                    for (int i = 0; i < C::NBR; ++i)
-                        load_codes_buf<V>(crs, voff * 2u, (row0 + (uint32_t)i * nx) * 2u, bb[i]);
-                    __builtin_amdgcn_sched_barrier(0);
-                };
-                static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
-                if (a.n_out) st.prefetch(a, lane);
-                static_for<0, NBT>([&](auto bI) {
-                    constexpr int b = decltype(bI)::value;
-                    constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
-                    dec_batch<DIM, B, V, C::NBR, true>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb, x0,
-                                                       true, gmask, lane, corrupt, ors,
-                                                       ((uint32_t)zl * ny + yb) * nx * 4u);
-                    if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
-                });
-                if (leader && st.rank != st.oe - st.os) corrupt = true;
-            }
+                        for (int i = 0; i < C::NBR; ++i) {
+                            const uint32_t yl = (uint32_t)((b % YB) * C::NBR + i);
+                            const uint32_t yc = FULL ? yl : min(yl, ymax);
+                            load_codes_buf<V>(crs, lvoff * 2u, (zc * ny + yc) * nx * 2u, bb[i]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    };
+                    static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
+                    if (a.n_out) {
+                        // the last lane of the chunk's last block inside the field
+                        const uint32_t nvb = FULL ? (uint32_t)C::BPC : min((uint32_t)C::BPC, a.g.nbx - bx0);
+                        st.prefetch(a, lane, (int)(nvb * C::GPB) - 1);
+                    }
+                    static_for<0, NBT>([&](auto bI) {
+                        constexpr int b = decltype(bI)::value;
+                        constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
+                        if (FULL || (uint32_t)zl <= zmax)  // uniform
+                            dec_batch<DIM, B, V, C::NBR, FULL>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb,
+                                                               x0, xin, gmask, lane, corrupt, ors,
+                                                               ((uint32_t)zl * ny + yb) * nx * 4u);
+                        if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
+                    });
+                    if (leader && gvalid && st.rank != st.oe - st.os) corrupt = true;
+                }
+            };
+            if ((tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny && (bz + 1) * C::BZ <= nz)
+                run(Idx<1>{});
+            else
+                run(Idx<0>{});
         } else {
             for (int ch = 0; ch < C::XCH; ++ch) {
                 const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
@@ -514,7 +538,7 @@ template <int DIM, int B, int V>
 __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * kWaves + wave;
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
     if (t >= a.g.n_tiles) return;  // tile 0 (which initialises the result) always exists
     decode_tile<DIM, B, V>(a, t, lane);
 }

@@ -24,6 +24,18 @@ constexpr int kStageCap = 256;            // LDS outlier staging entries per wav
 constexpr uint32_t kOriginFlag = 0x80000000u;
 constexpr int kTileTarget = 1024;         // minimum cells per tile (1-D, 2-D)
 
+// The dispatcher hands the workgroups of a launch to the 8 XCDs in turn
+// (workgroup i to XCD i mod 8), and every XCD has an L2 of its own. Tile
+// kernels renumber their workgroups so that each XCD receives one contiguous
+// range of tiles: neighbouring tiles of a row, which share cache lines
+// whenever a row is not a whole number of 128-byte lines, are then read and
+// written through one L2 instead of two (a bijection of [0, n)).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    const uint32_t x = b % kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 constexpr int ST_OK = 0, ST_EINVAL = -1, ST_ERANGE = -2, ST_ECAPACITY = -3, ST_ECORRUPT = -6;
 constexpr int PAD_ZERO = 0, PAD_BLOCK = 1, PAD_EDGE = 2, PAD_GLOBAL = 3;
 constexpr int PAD_BLOCK_MIN = 4, PAD_BLOCK_MAX = 5, PAD_GLOBAL_MIN = 6, PAD_GLOBAL_MAX = 7;
@@ -569,38 +581,35 @@ __device__ __forceinline__ void store_f(float* p, const float (&v)[V]) {
     }
 }
 
-// Write-through store: a relaxed system-scope store (sc0 sc1) goes through
-// the L2 to memory while the kernel runs instead of waiting, dirty, for the
-// write-back at the end of the kernel; on the encode pattern it is faster
-// than both plain and nontemporal stores. It is an ordinary store otherwise:
-// no ordering is implied.
-template <typename T>
-__device__ __forceinline__ void store_wt(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
+// Codes are stored and loaded with the default cache policy. A row of codes
+// that does not start on a 128-byte line shares its first and last lines
+// with the neighbouring tiles' rows: write-through stores send each part of
+// such a line to memory on its own (a partial-line write), and nontemporal
+// loads do not keep the line in the L2 for the neighbour, so it is fetched
+// twice. On rows of 450 or 480 cells this cost the decode 45-65 % and the
+// encode up to 25 %; aligned rows run as fast with either policy.
 // V uint16 codes, packed in 16-bit halves of 32-bit words
 template <int V>
 __device__ __forceinline__ void store_codes(uint16_t* p, const uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        store_wt(p, (uint16_t)c[0]);
+        *p = (uint16_t)c[0];
     } else if constexpr (V == 2) {
-        store_wt(reinterpret_cast<uint32_t*>(p), c[0] | (c[1] << 16));
+        *reinterpret_cast<uint32_t*>(p) = c[0] | (c[1] << 16);
     } else {
         const uint64_t w = (uint64_t)(c[0] | (c[1] << 16)) | ((uint64_t)(c[2] | (c[3] << 16)) << 32);
-        store_wt(reinterpret_cast<uint64_t*>(p), w);
+        *reinterpret_cast<uint64_t*>(p) = w;
     }
 }
 
 template <int V>
 __device__ __forceinline__ void load_codes(const uint16_t* p, uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        c[0] = __builtin_nontemporal_load(p);
+        c[0] = *(p);
     } else if constexpr (V == 2) {
-        uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+        uint32_t w = *(reinterpret_cast<const uint32_t*>(p));
         c[0] = w & 0xffffu; c[1] = w >> 16;
     } else {
-        u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+        u32x2 w = *(reinterpret_cast<const u32x2*>(p));
         c[0] = w.x & 0xffffu; c[1] = w.x >> 16; c[2] = w.y & 0xffffu; c[3] = w.y >> 16;
     }
 }
@@ -615,7 +624,7 @@ __device__ __forceinline__ void load_codes(const uint16_t* p, uint32_t (&c)[V]) 
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int kRsrcFlags = 0x00020000;
 constexpr int kPolNT = 2;   // nontemporal
-constexpr int kPolWT = 17;  // sc0 sc1: write-through (see store_wt)
+constexpr int kPolDefault = 0;  // codes (see store_codes)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ Rsrc make_rsrc(const void* base) {
@@ -658,25 +667,25 @@ __device__ __forceinline__ void store_f_buf(Rsrc rs, uint32_t voff, uint32_t sof
 template <int V>
 __device__ __forceinline__ void store_codes_buf(Rsrc rs, uint32_t voff, uint32_t soff, const uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)c[0], rs, (int)voff, (int)soff, kPolWT);
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)c[0], rs, (int)voff, (int)soff, kPolDefault);
     } else if constexpr (V == 2) {
-        __builtin_amdgcn_raw_buffer_store_b32(c[0] | (c[1] << 16), rs, (int)voff, (int)soff, kPolWT);
+        __builtin_amdgcn_raw_buffer_store_b32(c[0] | (c[1] << 16), rs, (int)voff, (int)soff, kPolDefault);
     } else {
         const u32x2 w = {c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
-        __builtin_amdgcn_raw_buffer_store_b64(w, rs, (int)voff, (int)soff, kPolWT);
+        __builtin_amdgcn_raw_buffer_store_b64(w, rs, (int)voff, (int)soff, kPolDefault);
     }
 }
 
 template <int V>
 __device__ __forceinline__ void load_codes_buf(Rsrc rs, uint32_t voff, uint32_t soff, uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        c[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)voff, (int)soff, kPolNT);
+        c[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)voff, (int)soff, kPolDefault);
     } else if constexpr (V == 2) {
-        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, kPolNT);
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, kPolDefault);
         c[0] = w & 0xffffu;
         c[1] = w >> 16;
     } else {
-        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, kPolNT));
+        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, kPolDefault));
         c[0] = w.x & 0xffffu;
         c[1] = w.x >> 16;
         c[2] = w.y & 0xffffu;

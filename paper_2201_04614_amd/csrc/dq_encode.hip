@@ -491,47 +491,72 @@ __device__ __forceinline__ void encode_tile(const EncArgs& a, uint4* sbuf, const
                                                            gpad, tile_total);
                 }
             }
-        } else if (C::NBT * C::NBR <= kMaxUnrollRows && (tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny &&
-                   (bz + 1) * C::BZ <= nz && (uint64_t)((C::BZ - 1) * ny + C::BY) * nx * 4u < 0x7fffffffull) {
-            // Interior tile: every block complete. The block row is one
-            // straight-line sequence of NBT batches with kPipeDepth batches
-            // of loads in flight ahead of the one being computed; loads and
-            // code stores are unconditional and addressed from wave-uniform
-            // row bases, so each wait retires exactly the batch it needs.
+        } else if (C::NBT * C::NBR <= kMaxUnrollRows && (uint64_t)((C::BZ - 1) * ny + C::BY) * nx * 4u < 0x7fffffffull) {
+            // Pipelined tile: the block row is one straight-line sequence of
+            // NBT batches with kPipeDepth batches of loads in flight ahead of
+            // the one being computed, so each wait retires exactly the batch
+            // it needs. Interior tiles (FULL: every block complete) load and
+            // store unconditionally from wave-uniform row bases. A tile that
+            // reaches past the field's end takes the same sequence with the
+            // loads clamped to the last column, row and plane (always in
+            // bounds), the stores under per-lane conditions and the batches
+            // of planes past the end skipped.
             constexpr int NBT = C::NBT;
             constexpr int D = cmin(NBT, kPipeDepth);
             constexpr int YB = C::BY / C::NBR;  // batches per plane
             const uint32_t voff = (uint32_t)lane * V;
-            for (int ch = 0; ch < C::XCH; ++ch) {
-                const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
-                const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
-                const uint32_t x0 = bx0 * B + voff;
-                const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
-                const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
-                const Rsrc xrs = make_rsrc(a.x + base);
-                const Rsrc crs = make_rsrc(a.codes + base);
-                EncState<DIM, B, V> st;
-                st.init();
-                float buf[D][C::NBR][V];
-                auto load = [&](auto bI, float (&bb)[C::NBR][V]) {
-                    constexpr int b = decltype(bI)::value;
-                    const uint32_t row0 = ((uint32_t)(b / YB) * ny + (b % YB) * C::NBR) * nx;
+            auto run = [&](auto fullI) {
+                constexpr bool FULL = decltype(fullI)::value != 0;
+                // last local plane and row inside the field
+                const uint32_t zmax = FULL ? (uint32_t)C::BZ - 1u : min((uint32_t)C::BZ, nz - bz * C::BZ) - 1u;
+                const uint32_t ymax = FULL ? (uint32_t)C::BY - 1u : min((uint32_t)C::BY, ny - by * C::BY) - 1u;
+                for (int ch = 0; ch < C::XCH; ++ch) {
+                    const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
+                    if (!FULL && bx0 >= a.g.nbx) break;  // uniform
+                    const uint32_t bx = bx0 + (uint32_t)(lane / C::GPB);
+                    const bool gvalid = FULL || bx < a.g.nbx;
+                    const uint32_t x0 = bx0 * B + voff;
+                    const bool xin = FULL || x0 < nx;
+                    // nx is a multiple of V, so a chunk inside the field holds
+                    // at least V columns and the clamped offset is >= 0
+                    const uint32_t lvoff = FULL ? voff : min(x0, nx - V) - bx0 * B;
+                    const uint32_t blk = (bz * a.g.nby + by) * a.g.nbx + bx;
+                    const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
+                    const Rsrc xrs = make_rsrc(a.x + base);
+                    const Rsrc crs = make_rsrc(a.codes + base);
+                    EncState<DIM, B, V> st;
+                    st.init();
+                    float buf[D][C::NBR][V];
+                    auto load = [&](auto bI, float (&bb)[C::NBR][V]) {
+                        constexpr int b = decltype(bI)::value;
+                        const uint32_t zc = FULL ? (uint32_t)(b / YB) : min((uint32_t)(b / YB), zmax);
 #pragma unroll
-                    for (int i = 0; i < C::NBR; ++i) load_f_buf<V>(xrs, voff * 4u, (row0 + (uint32_t)i * nx) * 4u, bb[i]);
-                    __builtin_amdgcn_sched_barrier(0);
-                };
-                static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
-                static_for<0, NBT>([&](auto bI) {
-                    constexpr int b = decltype(bI)::value;
-                    constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
-                    enc_batch<DIM, B, V, C::NBR, true>(a, st, w, buf[b % D], zl, yb, bz * B + zl, by * C::BY + yb,
-                                                       x0, true, leader, last, gmask, blk, r, twoeb, eb, bad, crs,
-                                                       ((uint32_t)zl * ny + yb) * nx * 2u);
-                    if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
-                });
-                tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, by, bz, blk, x0, true, leader, gpad,
-                                                       tile_total);
-            }
+                        for (int i = 0; i < C::NBR; ++i) {
+                            const uint32_t yl = (uint32_t)((b % YB) * C::NBR + i);
+                            const uint32_t yc = FULL ? yl : min(yl, ymax);
+                            load_f_buf<V>(xrs, lvoff * 4u, (zc * ny + yc) * nx * 4u, bb[i]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    };
+                    static_for<0, D>([&](auto bI) { load(bI, buf[decltype(bI)::value]); });
+                    static_for<0, NBT>([&](auto bI) {
+                        constexpr int b = decltype(bI)::value;
+                        constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
+                        if (FULL || (uint32_t)zl <= zmax)  // uniform
+                            enc_batch<DIM, B, V, C::NBR, FULL>(a, st, w, buf[b % D], zl, yb, bz * B + zl,
+                                                               by * C::BY + yb, x0, xin, leader, last, gmask, blk, r,
+                                                               twoeb, eb, bad, crs,
+                                                               ((uint32_t)zl * ny + yb) * nx * 2u);
+                        if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
+                    });
+                    tile_total += enc_block_end<DIM, B, V>(a, st, w, bx, by, bz, blk, x0, gvalid, leader, gpad,
+                                                           tile_total);
+                }
+            };
+            if ((tx + 1) * C::BPT * B <= nx && (by + 1) * C::BY <= ny && (bz + 1) * C::BZ <= nz)
+                run(Idx<1>{});
+            else
+                run(Idx<0>{});
         } else {
             for (int ch = 0; ch < C::XCH; ++ch) {
                 const uint32_t bx0 = tx * C::BPT + ch * C::BPC;
@@ -713,7 +738,7 @@ __global__ __launch_bounds__(kThreads, (V == 1 ? 4 : 1)) void k_encode(EncArgs a
     __shared__ uint4 sbuf_all[kWaves][kStageCap];
     const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * kWaves + wave;
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
     if (t >= a.g.n_tiles) return;
     int st_in = 0;
     const Bound bd = encode_bound(a, st_in, lane, t == 0);
