@@ -150,6 +150,10 @@ CompressLayout compress_layout(const dq_params* p, uint64_t out_cap) {
 // Tag of a decompress call (see status_init_tagged): distinct for every call
 // of the process, never 0, salted per process so that a result buffer left
 // over from another process is unlikely to carry the same tag.
+bool codes_rows_on_lines(const Geom& g, int dim, const void* codes) {
+    return (reinterpret_cast<uintptr_t>(codes) & 127u) == 0u && (dim == 1 || g.nx % 64u == 0u);
+}
+
 uint32_t next_tag() {
     static std::atomic<uint32_t> counter{0};
     static const uint32_t salt = [] {
@@ -422,7 +426,8 @@ dq_status decompress_impl(const dq_params* p, double eb_abs, uint64_t n_out, con
     da.pad_mode = p->pad_mode;
     const dim3 grid((pl.g.n_tiles + kWaves - 1) / kWaves);
     if (hooks && hooks->ev_before) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_before), stream);
-    if (!launch_decode(pl.dim, pl.B, pl.V, da, grid, stream)) return DQ_ENOTSUP;
+    if (!launch_decode(pl.dim, pl.B, pl.V, da, grid, stream, codes_rows_on_lines(pl.g, pl.dim, codes)))
+        return DQ_ENOTSUP;
     if (hooks && hooks->ev_after) (void)hipEventRecord(reinterpret_cast<hipEvent_t>(hooks->ev_after), stream);
     return check_launch();
 }

@@ -303,8 +303,8 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
 }
 
 
-// Tile t of the call a, by one wave.
-template <int DIM, int B, int V>
+// Tile t of the call a, by one wave (NTC: nontemporal code loads).
+template <int DIM, int B, int V, bool NTC = false>
 __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const int lane) {
     using C = Cfg<DIM, B, V>;
     if (a.src) {  // the outlier count and bound of the compress call that wrote this stream
@@ -346,7 +346,7 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
 #pragma unroll
                 for (int i = 0; i < C::NBR; ++i) {
                     const uint32_t x0 = (tx * C::BPT + (cb + i) * C::BPC) * B + (uint32_t)lane * V;
-                    load_codes<V>(a.codes + min(x0, nx - V), c[i]);  // clamped: always in bounds
+                    load_codes<V, NTC>(a.codes + min(x0, nx - V), c[i]);  // clamped: always in bounds
                 }
 #pragma unroll
                 for (int i = 0; i < C::NBR; ++i) {
@@ -400,7 +400,7 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
                         for (int i = 0; i < C::NBR; ++i) {
                             const uint32_t yl = (uint32_t)((b % YB) * C::NBR + i);
                             const uint32_t yc = FULL ? yl : min(yl, ymax);
-                            load_codes_buf<V>(crs, lvoff * 2u, (zc * ny + yc) * nx * 2u, bb[i]);
+                            load_codes_buf<V, NTC>(crs, lvoff * 2u, (zc * ny + yc) * nx * 2u, bb[i]);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     };
@@ -446,7 +446,7 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
 #pragma unroll
                     for (int i = 0; i < C::NBR; ++i) {
                         const uint32_t y = min(by * B + yb + i, ny - 1);  // clamped row
-                        load_codes<V>(a.codes + ((uint64_t)z * ny + y) * nx + xl, buf[i]);
+                        load_codes<V, NTC>(a.codes + ((uint64_t)z * ny + y) * nx + xl, buf[i]);
                     }
                     // keep the loads here: the scheduler would otherwise sink
                     // them to their first use and serialise memory and compute
@@ -497,7 +497,7 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
 #pragma unroll
                 for (int i = 0; i < C::NBR; ++i) {
                     const uint32_t x0 = bx * B + (cb + i) * C::CX + (uint32_t)lane * V;
-                    load_codes<V>(a.codes + min(x0, nx - V), c[i]);
+                    load_codes<V, NTC>(a.codes + min(x0, nx - V), c[i]);
                 }
 #pragma unroll
                 for (int i = 0; i < C::NBR; ++i) {
@@ -534,13 +534,13 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
     if (ballot(corrupt) && lane == 0) status_corrupt_tagged(a.res_word, a.tag);
 }
 
-template <int DIM, int B, int V>
+template <int DIM, int B, int V, bool NTC>
 __global__ __launch_bounds__(kThreads) void k_decode(DecArgs a) {
     const int wave = (int)uniform(threadIdx.x >> 6);  // scalar: tile math stays in SGPRs
     const int lane = threadIdx.x & 63;
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x) * kWaves + wave;
     if (t >= a.g.n_tiles) return;  // tile 0 (which initialises the result) always exists
-    decode_tile<DIM, B, V>(a, t, lane);
+    decode_tile<DIM, B, V, NTC>(a, t, lane);
 }
 
 // Persistent decode of a batch of fields of one configuration, draining the
@@ -572,10 +572,13 @@ __global__ __launch_bounds__(kThreads) void k_decode_batch(const DecArgs* __rest
 
 // instantiated only for the configurations of this object's dimensionality
 template <int D, int BB, int VV>
-static bool try_launch_decode(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
+static bool try_launch_decode(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream, bool nt_codes) {
     if constexpr (D == DQ_DIM) {
         if (block == BB && v == VV) {
-            hipLaunchKernelGGL((k_decode<D, BB, VV>), grid, dim3(kThreads), 0, stream, a);
+            if (nt_codes)
+                hipLaunchKernelGGL((k_decode<D, BB, VV, true>), grid, dim3(kThreads), 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_decode<D, BB, VV, false>), grid, dim3(kThreads), 0, stream, a);
             return true;
         }
     }
@@ -583,9 +586,10 @@ static bool try_launch_decode(int block, int v, const DecArgs& a, dim3 grid, hip
 }
 
 #define DQ_DEC_CASE(D, BB, VV) \
-    if (try_launch_decode<D, BB, VV>(block, v, a, grid, stream)) return true;
+    if (try_launch_decode<D, BB, VV>(block, v, a, grid, stream, nt_codes)) return true;
 
-bool DQ_CAT(launch_decode_dim, DQ_DIM)(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
+bool DQ_CAT(launch_decode_dim, DQ_DIM)(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream,
+                                       bool nt_codes) {
     DQ_CONFIGS(DQ_DEC_CASE)
     return false;
 }

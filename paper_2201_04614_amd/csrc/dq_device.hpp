@@ -581,13 +581,15 @@ __device__ __forceinline__ void store_f(float* p, const float (&v)[V]) {
     }
 }
 
-// Codes are stored and loaded with the default cache policy. A row of codes
-// that does not start on a 128-byte line shares its first and last lines
-// with the neighbouring tiles' rows: write-through stores send each part of
-// such a line to memory on its own (a partial-line write), and nontemporal
-// loads do not keep the line in the L2 for the neighbour, so it is fetched
-// twice. On rows of 450 or 480 cells this cost the decode 45-65 % and the
-// encode up to 25 %; aligned rows run as fast with either policy.
+// Codes are stored with the default (write-back) cache policy, and loaded
+// with it wherever a row of codes may not start on a 128-byte line. Such a
+// row shares its first and last lines with the neighbouring tiles' rows:
+// write-through stores sent each part of a shared line to memory on its own
+// (a partial-line write), and nontemporal loads did not keep the line in the
+// L2 for the neighbour, so it was fetched twice (on rows of 450 or 480 cells
+// the decode took 45-65 % longer, the encode up to 25 %). Fields whose rows
+// all start on lines are decoded with nontemporal loads, which leave the L2
+// and the Infinity Cache to the data that is read again.
 // V uint16 codes, packed in 16-bit halves of 32-bit words
 template <int V>
 __device__ __forceinline__ void store_codes(uint16_t* p, const uint32_t (&c)[V]) {
@@ -601,15 +603,21 @@ __device__ __forceinline__ void store_codes(uint16_t* p, const uint32_t (&c)[V])
     }
 }
 
-template <int V>
+// NT: nontemporal loads (see the note on codes above for when they are not)
+template <int V, bool NT = false>
 __device__ __forceinline__ void load_codes(const uint16_t* p, uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        c[0] = *(p);
+        if constexpr (NT) c[0] = __builtin_nontemporal_load(p);
+        else c[0] = *p;
     } else if constexpr (V == 2) {
-        uint32_t w = *(reinterpret_cast<const uint32_t*>(p));
+        uint32_t w;
+        if constexpr (NT) w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+        else w = *reinterpret_cast<const uint32_t*>(p);
         c[0] = w & 0xffffu; c[1] = w >> 16;
     } else {
-        u32x2 w = *(reinterpret_cast<const u32x2*>(p));
+        u32x2 w;
+        if constexpr (NT) w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+        else w = *reinterpret_cast<const u32x2*>(p);
         c[0] = w.x & 0xffffu; c[1] = w.x >> 16; c[2] = w.y & 0xffffu; c[3] = w.y >> 16;
     }
 }
@@ -676,16 +684,16 @@ __device__ __forceinline__ void store_codes_buf(Rsrc rs, uint32_t voff, uint32_t
     }
 }
 
-template <int V>
+template <int V, bool NT = false>
 __device__ __forceinline__ void load_codes_buf(Rsrc rs, uint32_t voff, uint32_t soff, uint32_t (&c)[V]) {
     if constexpr (V == 1) {
-        c[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)voff, (int)soff, kPolDefault);
+        c[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)voff, (int)soff, NT ? kPolNT : kPolDefault);
     } else if constexpr (V == 2) {
-        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, kPolDefault);
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, NT ? kPolNT : kPolDefault);
         c[0] = w & 0xffffu;
         c[1] = w >> 16;
     } else {
-        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, kPolDefault));
+        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, NT ? kPolNT : kPolDefault));
         c[0] = w.x & 0xffffu;
         c[1] = w.x >> 16;
         c[2] = w.y & 0xffffu;

@@ -38,6 +38,10 @@ bool make_plan(const dq_params* p, const void* fptr, const void* cptr, Plan& pl)
 CompressLayout compress_layout(const dq_params* p, uint64_t out_cap);
 // A tag distinct for every call of the process, never 0.
 uint32_t next_tag();
+// True when every row of the codes starts on a 128-byte line (an aligned
+// buffer, and rows of a multiple of 64 cells in 2-D and 3-D): the decode then
+// loads the codes nontemporally (see the note on codes in dq_device.hpp).
+bool codes_rows_on_lines(const Geom& g, int dim, const void* codes);
 
 }  // namespace host
 }  // namespace dq

@@ -34,9 +34,9 @@ namespace dq {
 bool launch_encode_dim1(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
 bool launch_encode_dim2(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
 bool launch_encode_dim3(int block, int v, const EncArgs& a, dim3 grid, hipStream_t stream);
-bool launch_decode_dim1(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
-bool launch_decode_dim2(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
-bool launch_decode_dim3(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream);
+bool launch_decode_dim1(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream, bool nt_codes);
+bool launch_decode_dim2(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream, bool nt_codes);
+bool launch_decode_dim3(int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream, bool nt_codes);
 
 // Workgroups of the encode kernel that fit on one compute unit at once (0 if
 // not built or unknown); one workgroup holds one wave per SIMD.
@@ -54,10 +54,11 @@ inline bool launch_encode(int dim, int block, int v, const EncArgs& a, dim3 grid
          : dim == 2 ? launch_encode_dim2(block, v, a, grid, stream)
          : dim == 3 ? launch_encode_dim3(block, v, a, grid, stream) : false;
 }
-inline bool launch_decode(int dim, int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream) {
-    return dim == 1 ? launch_decode_dim1(block, v, a, grid, stream)
-         : dim == 2 ? launch_decode_dim2(block, v, a, grid, stream)
-         : dim == 3 ? launch_decode_dim3(block, v, a, grid, stream) : false;
+// nt_codes: nontemporal code loads (every row of the codes starts on a 128-byte line)
+inline bool launch_decode(int dim, int block, int v, const DecArgs& a, dim3 grid, hipStream_t stream, bool nt_codes) {
+    return dim == 1 ? launch_decode_dim1(block, v, a, grid, stream, nt_codes)
+         : dim == 2 ? launch_decode_dim2(block, v, a, grid, stream, nt_codes)
+         : dim == 3 ? launch_decode_dim3(block, v, a, grid, stream, nt_codes) : false;
 }
 
 // Blocks per tile along x of a configuration (0 if not built).
