@@ -233,8 +233,9 @@ __device__ __forceinline__ void dec_row(const DecArgs& a, DecState<DIM, B, V>& s
 // whole wave, the prefix sums and dequantisation are branch-free across rows.
 // FULL: every row and lane lies inside the field; row i is written through
 // the tile's buffer resource ors at scalar offset osoff + i*nx*4, with no
-// per-lane condition.
-template <int DIM, int B, int V, int NR, bool FULL>
+// per-lane condition. PB (a pipelined tile past the field's end): the same
+// stores, with lanes and rows outside the field sent out of range.
+template <int DIM, int B, int V, int NR, bool FULL, bool PB = false>
 __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[NR][V],
                                           int yb, uint32_t z, uint32_t y0, uint32_t x0, bool xin, uint64_t gmask,
                                           int lane, bool& corrupt, Rsrc ors = Rsrc(), uint32_t osoff = 0) {
@@ -297,6 +298,9 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
         }
         if constexpr (FULL)
             store_f_buf<V>(ors, (uint32_t)(lane * V * 4), osoff + (uint32_t)i * nx * 4u, o);
+        else if constexpr (PB)  // through the tile's resource, lanes and rows outside the field dropped
+            store_f_buf<V>(ors, (xin && y0 + i < ny) ? (uint32_t)(lane * V * 4) : kOutOfRange,
+                           osoff + (uint32_t)i * nx * 4u, o);
         else if (xin && y0 + i < ny)
             store_f<V>(a.x_hat + ((uint64_t)z * ny + y0 + i) * nx + x0, o);
     }
@@ -414,7 +418,7 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
                         constexpr int b = decltype(bI)::value;
                         constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
                         if (FULL || (uint32_t)zl <= zmax)  // uniform
-                            dec_batch<DIM, B, V, C::NBR, FULL>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb,
+                            dec_batch<DIM, B, V, C::NBR, FULL, !FULL>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb,
                                                                x0, xin, gmask, lane, corrupt, ors,
                                                                ((uint32_t)zl * ny + yb) * nx * 4u);
                         if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);

@@ -635,6 +635,15 @@ constexpr int kPolNT = 2;   // nontemporal
 constexpr int kPolDefault = 0;  // codes (see store_codes)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// A lane offset past the resource's range (2^31 - 1 bytes): a raw buffer
+// access there is dropped by the hardware (a store writes nothing). Tiles
+// that reach past the field's end store through it for their lanes and rows
+// outside the field, so their stores stay unconditional like an interior
+// tile's. The scalar row offset added to it stays below 2^31 - 1 wherever
+// it is used (the pipelined path's tile-span bound), so the sum cannot wrap
+// back into range.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
 __device__ __forceinline__ Rsrc make_rsrc(const void* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, kRsrcFlags);
 }

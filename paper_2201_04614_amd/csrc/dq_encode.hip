@@ -216,8 +216,9 @@ __device__ __forceinline__ void enc_row(const EncArgs& a, EncState<DIM, B, V>& s
 // of a 2-D/3-D step. FULL: every row and lane lies inside the field; the
 // codes of row i are stored through the tile's buffer resource crs at
 // scalar offset csoff + i*nx*2, with no per-lane condition, so every store
-// is issued on every path.
-template <int DIM, int B, int V, int NR, bool FULL>
+// is issued on every path. PB (a pipelined tile past the field's end): the
+// same stores, with lanes and rows outside the field sent out of range.
+template <int DIM, int B, int V, int NR, bool FULL, bool PB = false>
 __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>& st, WaveCtx& w,
                                           const float (&xv)[NR][V], int zl, int yb, uint32_t z, uint32_t y0,
                                           uint32_t x0, bool xin, bool leader, bool last, uint64_t gmask, uint32_t blk,
@@ -278,6 +279,9 @@ __device__ __forceinline__ void enc_batch(const EncArgs& a, EncState<DIM, B, V>&
         }
         if constexpr (FULL)
             store_codes_buf<V>(crs, (uint32_t)(w.lane * V * 2), csoff + (uint32_t)i * nx * 2u, code);
+        else if constexpr (PB)  // through the tile's resource, lanes and rows outside the field dropped
+            store_codes_buf<V>(crs, (xin && y0 + i < ny) ? (uint32_t)(w.lane * V * 2) : kOutOfRange,
+                               csoff + (uint32_t)i * nx * 2u, code);
         else if (xin && y0 + i < ny)
             store_codes<V>(a.codes + ((uint64_t)z * ny + y0 + i) * nx + x0, code);
     }
@@ -543,7 +547,7 @@ __device__ __forceinline__ void encode_tile(const EncArgs& a, uint4* sbuf, const
                         constexpr int b = decltype(bI)::value;
                         constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
                         if (FULL || (uint32_t)zl <= zmax)  // uniform
-                            enc_batch<DIM, B, V, C::NBR, FULL>(a, st, w, buf[b % D], zl, yb, bz * B + zl,
+                            enc_batch<DIM, B, V, C::NBR, FULL, !FULL>(a, st, w, buf[b % D], zl, yb, bz * B + zl,
                                                                by * C::BY + yb, x0, xin, leader, last, gmask, blk, r,
                                                                twoeb, eb, bad, crs,
                                                                ((uint32_t)zl * ny + yb) * nx * 2u);
