@@ -235,10 +235,11 @@ __device__ __forceinline__ void dec_row(const DecArgs& a, DecState<DIM, B, V>& s
 // the tile's buffer resource ors at scalar offset osoff + i*nx*4, with no
 // per-lane condition. PB (a pipelined tile past the field's end): the same
 // stores, with lanes and rows outside the field sent out of range.
-template <int DIM, int B, int V, int NR, bool FULL, bool PB = false>
+template <int DIM, int B, int V, int NR, bool FULL, bool PB = false, bool SPLIT = false>
 __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>& st, const uint32_t (&c)[NR][V],
                                           int yb, uint32_t z, uint32_t y0, uint32_t x0, bool xin, uint64_t gmask,
-                                          int lane, bool& corrupt, Rsrc ors = Rsrc(), uint32_t osoff = 0) {
+                                          int lane, bool& corrupt, Rsrc ors = Rsrc(), uint32_t osoff = 0,
+                                          uint32_t obase = 0) {
     using C = Cfg<DIM, B, V>;
     const uint32_t R = (uint32_t)a.R;
     const uint32_t ny = a.g.ny, nx = a.g.nx;
@@ -296,19 +297,35 @@ __device__ __forceinline__ void dec_batch(const DecArgs& a, DecState<DIM, B, V>&
             const int32_t q = (int32_t)(p + st.peff);
             o[j] = (float)((double)q * a.twoeb);
         }
-        if constexpr (FULL)
+        if constexpr ((FULL || PB) && SPLIT) {
+            // two unconditional stores, each lane in one of them: nontemporal for
+            // lanes on whole lines of the segment, write-back for lanes on lines
+            // shared with the neighbouring segment (so the two parts merge in the
+            // L2), the other store of the pair out of range
+            const uint32_t soff = osoff + (uint32_t)i * nx * 4u;
+            const uint32_t lof = (uint32_t)(lane * V * 4);
+            const uint32_t xs = x0 - (uint32_t)lane * V;  // the segment's first column
+            const uint32_t lo = obase + soff;
+            const uint32_t hi = lo + (FULL ? 256u * V : (min(xs + 64u * V, nx) - xs) * 4u);
+            const bool valid = FULL || (xin && y0 + i < ny);
+            const bool sh = shares_line(lo + lof, lo, hi);
+            store_f_buf<V>(ors, (valid && !sh) ? lof : kOutOfRange, soff, o);
+            store_f_buf<V, kPolDefault>(ors, (valid && sh) ? lof : kOutOfRange, soff, o);
+        } else if constexpr (FULL) {
             store_f_buf<V>(ors, (uint32_t)(lane * V * 4), osoff + (uint32_t)i * nx * 4u, o);
-        else if constexpr (PB)  // through the tile's resource, lanes and rows outside the field dropped
+        } else if constexpr (PB) {  // through the tile's resource, lanes and rows outside the field dropped
             store_f_buf<V>(ors, (xin && y0 + i < ny) ? (uint32_t)(lane * V * 4) : kOutOfRange,
                            osoff + (uint32_t)i * nx * 4u, o);
-        else if (xin && y0 + i < ny)
+        } else if (xin && y0 + i < ny) {
             store_f<V>(a.x_hat + ((uint64_t)z * ny + y0 + i) * nx + x0, o);
+        }
     }
 }
 
 
-// Tile t of the call a, by one wave (NTC: nontemporal code loads).
-template <int DIM, int B, int V, bool NTC = false>
+// Tile t of the call a, by one wave (NTC: nontemporal code loads; SPLIT:
+// decoded rows stored as a nontemporal / write-back pair, see dec_batch).
+template <int DIM, int B, int V, bool NTC = false, bool SPLIT = false>
 __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const int lane) {
     using C = Cfg<DIM, B, V>;
     if (a.src) {  // the outlier count and bound of the compress call that wrote this stream
@@ -394,6 +411,7 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
                     const uint64_t base = ((uint64_t)(bz * B) * ny + by * C::BY) * nx + bx0 * B;
                     const Rsrc crs = make_rsrc(a.codes + base);
                     const Rsrc ors = make_rsrc(a.x_hat + base);
+                    const uint32_t obase = (uint32_t)reinterpret_cast<uintptr_t>(a.x_hat + base);
                     DecState<DIM, B, V> st;
                     st.init(a, blk, gvalid);
                     uint32_t buf[D][C::NBR][V];
@@ -418,9 +436,9 @@ __device__ __forceinline__ void decode_tile(DecArgs a, const uint32_t t, const i
                         constexpr int b = decltype(bI)::value;
                         constexpr int zl = b / YB, yb = (b % YB) * C::NBR;
                         if (FULL || (uint32_t)zl <= zmax)  // uniform
-                            dec_batch<DIM, B, V, C::NBR, FULL, !FULL>(a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb,
-                                                               x0, xin, gmask, lane, corrupt, ors,
-                                                               ((uint32_t)zl * ny + yb) * nx * 4u);
+                            dec_batch<DIM, B, V, C::NBR, FULL, !FULL, SPLIT>(
+                                a, st, buf[b % D], yb, bz * B + zl, by * C::BY + yb, x0, xin, gmask, lane, corrupt,
+                                ors, ((uint32_t)zl * ny + yb) * nx * 4u, obase);
                         if constexpr (b + D < NBT) load(Idx<b + D>{}, buf[b % D]);
                     });
                     if (leader && gvalid && st.rank != st.oe - st.os) corrupt = true;
@@ -566,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_batch(const DecArgs* __rest
         const uint4 un = units[u];  // field, first tile, tiles
         const DecArgs& a = dec[uniform(un.x)];
         const uint32_t t0 = uniform(un.y), t1 = t0 + uniform(un.z);
-        for (uint32_t t = t0 + (uint32_t)wave; t < t1; t += kWaves) decode_tile<DIM, B, V>(a, t, lane);
+        for (uint32_t t = t0 + (uint32_t)wave; t < t1; t += kWaves) decode_tile<DIM, B, V, false, true>(a, t, lane);
     }
 }
 

@@ -667,18 +667,27 @@ __device__ __forceinline__ void load_f_buf(Rsrc rs, uint32_t voff, uint32_t soff
     }
 }
 
-template <int V>
+template <int V, int POL = kPolNT>
 __device__ __forceinline__ void store_f_buf(Rsrc rs, uint32_t voff, uint32_t soff, const float (&v)[V]) {
     if constexpr (V == 1) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[0]), rs, (int)voff, (int)soff, kPolNT);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[0]), rs, (int)voff, (int)soff, POL);
     } else if constexpr (V == 2) {
         const u32x2 t = {__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1])};
-        __builtin_amdgcn_raw_buffer_store_b64(t, rs, (int)voff, (int)soff, kPolNT);
+        __builtin_amdgcn_raw_buffer_store_b64(t, rs, (int)voff, (int)soff, POL);
     } else {
         const u32x4 t = {__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1]),
                          __builtin_bit_cast(uint32_t, v[2]), __builtin_bit_cast(uint32_t, v[3])};
-        __builtin_amdgcn_raw_buffer_store_b128(t, rs, (int)voff, (int)soff, kPolNT);
+        __builtin_amdgcn_raw_buffer_store_b128(t, rs, (int)voff, (int)soff, POL);
     }
+}
+
+// A lane of a decoded row segment whose 128-byte line the neighbouring
+// segment also writes (the next tile, or the next row): the segment starts or
+// ends inside that line. lo / hi: low 32 bits of the byte addresses of the
+// segment's first byte and of its end.
+__device__ __forceinline__ bool shares_line(uint32_t addr, uint32_t lo, uint32_t hi) {
+    const uint32_t l = addr & ~127u;
+    return (int32_t)(l - lo) < 0 || (int32_t)(hi - (l + 128u)) < 0;
 }
 
 template <int V>
